@@ -1,0 +1,187 @@
+"""Seeded synthetic inputs for the acceleration search.
+
+This module generates dedispersed-time-series-shaped float32 inputs and
+their ground truth. It holds none of the search's arithmetic (no Fourier
+transform, no response template, no harmonic sum, no threshold): both the
+FP64 oracle tests and the HIP path tests draw their inputs from here, so
+that each side sees the same bytes.
+
+Workload shapes follow the paper's test files (Table 1: a 52.4288 s FAST
+drift-scan file sampled at 0.2 ms, a 2100.224 s PMPS file) and its
+dedispersion plans (Tables 2-3), with white Gaussian noise standing in for
+the missing survey data.
+
+Signal model (stated here because generator and searches must agree on it):
+a sinusoid whose Fourier frequency, in bins of 1/T, is r0 at mid-observation
+and drifts by z0 bins over the observation, i.e. the phase in cycles is
+    phi(u) = phi0 + r0*u + z0*(u*u - u)/2,   u = n/N in [0, 1).
+Pulse trains replace cos(2 pi phi) by a von Mises profile of the same phase.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+BASE_SEED = 191212807
+
+
+def seed_for(config: int, series: int) -> int:
+    """Seed of one series: one PCG64 stream per (config, series)."""
+    return BASE_SEED + 1000 * int(config) + int(series)
+
+
+@dataclasses.dataclass
+class Injection:
+    series: int
+    kind: str            # "sine" | "pulse" | "tone"
+    r0: float            # fundamental Fourier frequency at mid-observation (bins)
+    z0: float            # fundamental drift over the observation (bins)
+    amp: float           # sine amplitude or pulse peak amplitude
+    duty: float = 0.0    # pulse FWHM as a fraction of the period
+    phase0: float = 0.0  # cycles
+
+    def as_dict(self):
+        return dataclasses.asdict(self)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    config: int
+    nsamp: int
+    nseries: int
+    tsamp: float
+    zmax: float
+    dz: float
+    numharm: int
+    sigma: float
+    injections: List[Injection]
+    noise: bool = True
+    series_idx: Optional[List[int]] = None   # which series of the batch were generated
+
+    @property
+    def tobs(self) -> float:
+        return self.nsamp * self.tsamp
+
+
+def _chirp_phase(n: int, r0: float, z0: float, phase0: float) -> np.ndarray:
+    u = np.arange(n, dtype=np.float64) / n
+    return phase0 + r0 * u + z0 * (u * u - u) * 0.5
+
+
+def add_sine(x: np.ndarray, r0: float, z0: float, amp: float, phase0: float = 0.0) -> None:
+    """x += amp*cos(2 pi phi(u)), summed in FP64."""
+    ph = _chirp_phase(x.shape[-1], r0, z0, phase0)
+    x += amp * np.cos(2.0 * np.pi * ph)
+
+
+def von_mises_kappa(duty: float) -> float:
+    """Concentration whose profile exp(kappa(cos 2 pi phi - 1)) has FWHM = duty."""
+    return math.log(2.0) / (1.0 - math.cos(math.pi * duty))
+
+
+def add_pulse(x: np.ndarray, r0: float, z0: float, amp: float, duty: float, phase0: float = 0.0) -> None:
+    """x += amp*exp(kappa(cos 2 pi phi(u) - 1)), a pulse train of the given FWHM duty."""
+    ph = _chirp_phase(x.shape[-1], r0, z0, phase0)
+    kappa = von_mises_kappa(duty)
+    x += amp * np.exp(kappa * (np.cos(2.0 * np.pi * ph) - 1.0))
+
+
+def _series(nsamp: int, seed: int, noise: bool) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if noise:
+        return rng.standard_normal(nsamp)
+    return np.zeros(nsamp, dtype=np.float64)
+
+
+def _render(wl: Workload, series_idx) -> np.ndarray:
+    out = np.empty((len(series_idx), wl.nsamp), dtype=np.float32)
+    by_series = {}
+    for inj in wl.injections:
+        by_series.setdefault(inj.series, []).append(inj)
+    for row, b in enumerate(series_idx):
+        x = _series(wl.nsamp, seed_for(wl.config, b), wl.noise)
+        for inj in by_series.get(b, []) + by_series.get(-1, []):
+            if inj.kind in ("sine", "tone"):
+                add_sine(x, inj.r0, inj.z0, inj.amp, inj.phase0)
+            elif inj.kind == "pulse":
+                add_pulse(x, inj.r0, inj.z0, inj.amp, inj.duty, inj.phase0)
+            else:
+                raise ValueError(inj.kind)
+        out[row] = x.astype(np.float32)
+    return out
+
+
+# --------------------------------------------------------------------------- configs
+
+def config1(noise: bool = True) -> Workload:
+    """One FAST-like series: 2^17 samples at 0.2 ms, a sinusoid at r0=10000.3, z0=7.5, a=0.05."""
+    inj = [Injection(series=0, kind="sine", r0=10000.3, z0=7.5, amp=0.05)]
+    return Workload("plain-fdas-1x2^17", 1, 1 << 17, 1, 2.0e-4, 20.0, 2.0, 1, 6.0, inj, noise=noise)
+
+
+def _pulsar_draws(rng, nsamp, tsamp, zabs_max, amp_lo=0.05, amp_hi=0.5):
+    tobs = nsamp * tsamp
+    period = math.exp(rng.uniform(math.log(1e-3), math.log(0.5)))   # seconds
+    duty = rng.uniform(0.02, 0.10)
+    z0 = rng.uniform(-zabs_max, zabs_max)
+    amp = math.exp(rng.uniform(math.log(amp_lo), math.log(amp_hi)))
+    r0 = tobs / period
+    phase0 = rng.uniform(0.0, 1.0)
+    return r0, z0, amp, duty, phase0
+
+
+def config2(nseries: int = 128, nsamp: int = 1 << 18) -> Workload:
+    """FAST drift-scan shaped batch: 128 x 2^18 at 0.2 ms; 8 series carry pulse trains."""
+    rng = np.random.Generator(np.random.PCG64(seed_for(2, 999)))
+    carriers = sorted(rng.choice(nseries, size=min(8, nseries), replace=False).tolist())
+    inj = []
+    for b in carriers:
+        r0, z0, amp, duty, ph = _pulsar_draws(rng, nsamp, 2.0e-4, 150.0)
+        inj.append(Injection(series=int(b), kind="pulse", r0=r0, z0=z0, amp=amp, duty=duty, phase0=ph))
+    return Workload("fast-batch-128x2^18", 2, nsamp, nseries, 2.0e-4, 200.0, 2.0, 8, 6.0, inj)
+
+
+def config3(nseries: int = 32, nsamp: int = 1 << 23) -> Workload:
+    """PMPS shaped long series: 32 x 2^23 at 250 us; binary-like pulse trains and RFI tones."""
+    tsamp = 2.5e-4
+    tobs = nsamp * tsamp
+    rng = np.random.Generator(np.random.PCG64(seed_for(3, 999)))
+    carriers = sorted(rng.choice(nseries, size=min(8, nseries), replace=False).tolist())
+    inj = []
+    for b in carriers:
+        r0, z0, amp, duty, ph = _pulsar_draws(rng, nsamp, tsamp, 200.0)
+        inj.append(Injection(series=int(b), kind="pulse", r0=r0, z0=z0, amp=amp, duty=duty, phase0=ph))
+    for f_hz, a in ((50.0, 0.3), (100.0, 0.1), (150.0, 0.05)):
+        inj.append(Injection(series=-1, kind="tone", r0=f_hz * tobs, z0=0.0, amp=a))
+    return Workload("pmps-long-32x2^23", 3, nsamp, nseries, tsamp, 200.0, 2.0, 16, 6.0, inj)
+
+
+def generate(wl: Workload, series_idx=None) -> np.ndarray:
+    """float32 [len(series_idx)][nsamp]; default: the whole batch."""
+    if series_idx is None:
+        series_idx = list(range(wl.nseries))
+    return _render(wl, list(series_idx))
+
+
+def small_batch(nseries: int, nsamp: int, tsamp: float, zmax: float, dz: float, numharm: int,
+                sigma: float = 6.0, config: int = 90, signals: int = 2, zabs_max: float = None,
+                amp_range=(0.05, 0.5), noise: bool = True) -> Workload:
+    """A small seeded batch with pulse trains in a few series, for parity tests."""
+    rng = np.random.Generator(np.random.PCG64(seed_for(config, 777)))
+    zabs = zmax * 0.75 if zabs_max is None else zabs_max
+    inj = []
+    for i in range(min(signals, nseries)):
+        b = int(rng.integers(0, nseries))
+        tobs = nsamp * tsamp
+        # keep the fundamental well inside the searched band
+        period = math.exp(rng.uniform(math.log(max(8 * tsamp, 2e-3)), math.log(tobs / 40.0)))
+        r0 = tobs / period
+        inj.append(Injection(series=b, kind="pulse", r0=r0, z0=rng.uniform(-zabs, zabs),
+                             amp=math.exp(rng.uniform(math.log(amp_range[0]), math.log(amp_range[1]))),
+                             duty=rng.uniform(0.02, 0.10), phase0=rng.uniform(0, 1)))
+    return Workload(f"small-{nseries}x{nsamp}", config, nsamp, nseries, tsamp, zmax, dz, numharm,
+                    sigma, inj, noise=noise)
