@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Throughput of the Fourier-domain acceleration search on one MI355X.
+
+One step = one fdas_search call over the whole batch: real FFT, median
+normalisation, power plane, harmonic sums, thresholding, compaction, drift
+argmax and the copy of the candidate list to host memory. The float32 series
+are resident in HBM when the timed region starts. Prints ONE JSON line.
+
+Default workload: the FAST drift-scan shaped batch (128 series x 2^18
+samples at 0.2 ms, zmax 200, dz 2, numharm 8, sigma 6; 8 series carry pulse
+trains), the configuration the cells/s metric is quoted on.
+
+Extra fields: "roofline" of the dominant kernel (device time per launch from
+HIP events recorded by the library on the search stream), "cpu_baseline" (the
+FP64 oracle on a bounded sample, timed on the host cores), "plain_path" (the
+same kernels driven one series at a time) and "phases_ms".
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "f-fdot cells/s (FDAS+harmsum) vs plain path at ≤1e-4 rel power error"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK = 157.3       # TFLOP/s, 256 CUs x 2.4 GHz x 256 FP32 flop/clk
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {"plane": "k_corr.hip", "harmsum": "k_harm.hip"}
+
+
+def _workload(config: int):
+    import synth
+    return {1: synth.config1, 2: synth.config2, 3: synth.config3}[config]()
+
+
+def kernel_hash(phase: str) -> str:
+    src = os.path.join(ROOT, "paper_1912_12807_amd", "csrc", KERNEL_SOURCES[phase])
+    h = hashlib.sha256()
+    for f in (src, os.path.join(ROOT, "paper_1912_12807_amd", "csrc", "dft_small.h")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(phase: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if still current."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh).get(f"{workload}:{phase}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_hash") != kernel_hash(phase):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def _oracle_series(args):
+    config, b = args
+    import oracle as O
+    import synth
+    wl = _workload(config)
+    x = synth.generate(wl, [b])[0]
+    t0 = time.perf_counter()
+    O.search_series(x, wl.tsamp, wl.zmax, wl.dz, wl.numharm, wl.sigma, series=b)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(config: int, wl, nr: int, nz: int, max_cores: int = 16):
+    """The FP64 oracle, one process per series (the paper's process-level strategy)."""
+    import multiprocessing as mp
+    cores = max(1, min(max_cores, len(os.sched_getaffinity(0))))
+    nser = min(cores, wl.nseries)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(nser) as pool:
+        per = pool.map(_oracle_series, [(config, b) for b in range(nser)])
+    wall = time.perf_counter() - t0
+    cells = nser * nr * nz
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": cells / wall, "unit": "cells/s", "cores": nser, "kind": "oracle",
+            "sample": f"{nser} of {wl.nseries} series of the same workload, one oracle process per "
+                      f"series, full plane + harmonic sums + candidates in FP64 "
+                      f"({wall:.1f} s wall, {sum(per) / nser:.1f} s per series)",
+            "cpu": model}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures the search on one GPU only; series shard across "
+              "GPUs without communication (see the design notes), but no multi-GPU figure is "
+              "produced here", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1912_12807_amd as fdas
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    fdas.load()
+    wl = _workload(args.config)
+    print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
+    x = torch.from_numpy(synth.generate(wl)).cuda()
+    rlo, nr, nz = fdas.geometry(wl.nsamp, wl.tsamp, wl.zmax, wl.dz)
+    cells = wl.nseries * nr * nz
+    plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1)
+    info = plan.info()
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        cands = plan.search(x, wl.tsamp, sigma=wl.sigma, cap=1 << 20)
+    torch.cuda.synchronize()
+    plan.profile(reset=True)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cands = plan.search(x, wl.tsamp, sigma=wl.sigma, cap=1 << 20)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile(reset=True)
+    ms_step = 1e3 * wall / args.steps
+    value = cells * args.steps / wall
+
+    # dominant kernel and its roofline
+    phases = {k: v[0] / args.steps for k, v in prof.items()}
+    dom = max(("plane", "harmsum"), key=lambda k: prof[k][0])
+    launches = max(1, prof[dom][1])
+    t_launch = prof[dom][0] / 1e3 / launches           # s
+    cells_launch = cells / (launches / args.steps)
+    L, mseg = info["seg_len"], info["mseg"]
+    Lv = L - 2 * mseg
+    NS = int(math.log2(wl.numharm)) + 1
+    if dom == "plane":
+        # overlap-save per (z row, parity, segment): inverse FFT 5 L log2 L, template product 6 L,
+        # power 3 L, over Lv outputs; plus one forward FFT per segment and z group (<= 8)
+        nseg = math.ceil((wl.nsamp // 2 - rlo) / Lv)
+        G = 1
+        while G < 8 and nz >= 2 * G * 12:
+            G *= 2
+        flops = (wl.nseries / (launches / args.steps)) * nseg * (
+            2 * nz * (5 * L * math.log2(L) + 9 * L) + G * (5 * L * math.log2(L) + 2 * L))
+        achieved = flops / t_launch / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VECTOR_PEAK, "kernel": "k_corr_power",
+                "per_unit": f"{flops / cells_launch:.1f} FLOP/cell"}
+    else:
+        byts = cells_launch * 4.0 + (cells_launch / nz) * NS * 4.0
+        achieved = byts / t_launch / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "kernel": "k_harmsum",
+                "per_unit": f"{4.0 + NS * 4.0 / nz:.3f} B/cell"}
+    roof["traffic"] = measured_traffic(dom, wl.name)
+    roof["launch_ms"] = t_launch * 1e3
+
+    plain = None
+    if not args.no_plain:
+        print("[bench] plain per-series path", file=sys.stderr, flush=True)
+        p1 = fdas.Plan(wl.nsamp, 1, wl.zmax, wl.dz, wl.numharm)
+        p1.search(x[0:1], wl.tsamp, sigma=wl.sigma)
+        torch.cuda.synchronize()
+        reps = 1
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for b in range(wl.nseries):
+                p1.search(x[b:b + 1], wl.tsamp, sigma=wl.sigma, cap=1 << 20)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        plain = {"value": cells * reps / pw, "unit": "cells/s", "ms_per_step": 1e3 * pw / reps,
+                 "what": "same kernels, one series per fdas_search call"}
+        p1.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.config, wl, nr, nz)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "nseries": wl.nseries, "nsamp": wl.nsamp, "tsamp": wl.tsamp,
+                   "zmax": wl.zmax, "dz": wl.dz, "numharm": wl.numharm, "sigma": wl.sigma,
+                   "cells_per_step": cells, "seg_len": L, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_path": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "candidates": int(len(cands)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * fdas.h - C ABI of the MI355X (gfx950) Fourier-domain acceleration search.
+ *
+ * The library searches a batch of dedispersed time series for periodic
+ * signals whose frequency drifts linearly over the observation: the pipeline
+ * steps "FFT the dedispersed series" and "search the spectrum for periodic
+ * signals with a frequency derivative bounded by zmax" (paper, Section 2,
+ * steps 3-4; zmax is the knob measured in Section 3.2, Table 4), followed by
+ * the candidate list that the sifting step (Section 2, step 5) consumes.
+ *
+ * The paper names these steps but does not state their mathematics. This
+ * library computes, per series b of length N (even) sampled at tsamp:
+ *   A_k   = sum_n x_n exp(-2 pi i k n / N), k = 0..N/2            (real FFT)
+ *   norm  = lower median of |A_k|^2 over k = 1..N/2-1, divided by ln 2
+ *           (or N * fixed_var), A^_k = A_k / sqrt(norm), A^_0 = A^_{N/2} = 0
+ *   P(r,z)= |sum_k A^_k conj rho(r-k, z)|^2 / E over |k - r| <= ceil(|z|/2)+K,
+ *           rho(q,z) = int_0^1 exp(2 pi i [q u + z (u^2-u)/2]) du, E the tap
+ *           energy; r = R/2 (half bins) at mid-observation, z = Zq*dz total drift
+ *   S_H   = sum_{k=1..H} P(round_half_up(R k/H), round_half_away(Zq k/H))
+ *   M_H(R)= max over Zq of S_H; a candidate is (b, H, R, Zq*) with
+ *           M_H(R) > T_H, where a sum of H unit exponentials exceeds T_H with
+ *           probability erfc(sigma/sqrt 2)/2 (single trial).
+ * H runs over 1, 2, 4, ..., numharm; R over [2 rlo H, N-1], rlo = ceil(flo T)
+ * (at least 1), T = N tsamp; Zq over [-zmax/dz, zmax/dz].
+ *
+ * Conventions: every pointer argument named *_dev is device memory of the
+ * current HIP device, *_host is host memory. Calls return an fdas_status and
+ * never abort or throw across the ABI. A plan is not thread safe: use one
+ * plan per host thread / stream. Calls that take a stream enqueue their work
+ * on it (NULL = the default stream) and return only after the work is done.
+ */
+#ifndef FDAS_H
+#define FDAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdas_plan_s *fdas_plan;
+
+typedef enum {
+    FDAS_OK = 0,
+    FDAS_E_INVAL = -1,        /* bad argument; nothing was launched */
+    FDAS_E_NOMEM = -2,        /* device or host allocation failed */
+    FDAS_E_DEVICE = -3,       /* a HIP call failed; sticky on the plan */
+    FDAS_E_TRUNC = -4,        /* more candidates than the caller's capacity */
+    FDAS_E_UNSUPPORTED = -5   /* valid but not supported (e.g. N not a power of two) */
+} fdas_status;
+
+typedef enum { FDAS_NORM_MEDIAN = 0, FDAS_NORM_FIXED = 1 } fdas_norm;
+
+typedef struct {
+    double  flo_hz;              /* lowest searched frequency, Hz (default 1.0) */
+    int32_t K;                   /* template half-width margin in bins (default 16) */
+    int32_t norm;                /* fdas_norm (default FDAS_NORM_MEDIAN) */
+    double  fixed_var;           /* FDAS_NORM_FIXED: norm = N * fixed_var (default 1.0) */
+    int64_t max_workspace_bytes; /* cap on the power-plane workspace (0 = automatic) */
+    int64_t max_candidates;      /* initial device candidate capacity (0 = 1<<20) */
+    int32_t seg_len;             /* overlap-save segment length L, 512..4096 (0 = automatic) */
+    int32_t profile;             /* nonzero: time every phase with HIP events (fdas_profile_read) */
+    int32_t reserved[6];         /* must be zero */
+} fdas_plan_opts;
+
+/* One candidate. r = r_idx/2 and z = z_idx*dz are the Fourier frequency
+ * (bins, mid-observation) and drift (bins) of the harm-th harmonic; the
+ * fundamental is r_fund = r_idx/(2 harm), z_fund = z_idx*dz/harm,
+ * f_hz = r_fund/T, fdot_hz_s = z_fund/T^2. power = M_H(R) in units of the
+ * mean noise power; sigma is its single-trial Gaussian-equivalent significance. */
+typedef struct {
+    int32_t series;
+    int32_t harm;
+    int64_t r_idx;
+    int32_t z_idx;
+    float   power;
+    double  sigma;
+    double  r_fund;
+    double  z_fund;
+    double  f_hz;
+    double  fdot_hz_s;
+} fdas_cand;
+
+/* Fill *opts with the defaults listed above. */
+void fdas_plan_opts_default(fdas_plan_opts *opts);
+
+/* Create a plan on the current HIP device for series of up to max_nsamp
+ * samples, batches of up to max_series series, drifts up to zmax (a whole
+ * multiple of dz) and up to numharm harmonics (1, 2, 4, 8, 16 or 32). The
+ * plan owns its device workspace and FP64-built response-template bank.
+ * opts may be NULL (defaults). On success *out is a new plan; on failure
+ * *out is NULL. Errors: FDAS_E_INVAL, FDAS_E_NOMEM, FDAS_E_DEVICE. */
+fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_series,
+                             double zmax, double dz, int32_t numharm,
+                             const fdas_plan_opts *opts);
+
+/* Destroy a plan and free its device memory (NULL is ignored). */
+void fdas_plan_destroy(fdas_plan p);
+
+/* Search series_dev (device, float32, contiguous [nseries][nsamp]).
+ * Writes min(total, cap) candidates to out_host, sorted by (series, harm,
+ * r_idx), and the total count to *n_total. Returns FDAS_E_TRUNC if total >
+ * cap (the first cap records in that order are written). zmax/dz/numharm may
+ * differ from the plan's (the template bank is rebuilt when zmax or dz
+ * change) but numharm may not exceed the plan's, nor nsamp/nseries its
+ * maxima. Errors: FDAS_E_INVAL when nsamp is odd, nsamp > max_nsamp, the
+ * searched band is empty, zmax is not a whole multiple of dz, numharm is not
+ * a power of two <= 32, sigma <= 0 or not finite, tsamp <= 0;
+ * FDAS_E_UNSUPPORTED when nsamp is not a power of two. NaN samples are not
+ * checked: they propagate into the powers. The caller keeps ownership of
+ * all buffers; the plan keeps no caller pointer after return. */
+fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
+                        double tsamp, double zmax, double dz, int32_t numharm, double sigma,
+                        fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream);
+
+/* The normalised power plane of each series: plane_dev (device, float32)
+ * receives [nseries][NZ][NR] with NZ = 2 zmax/dz + 1 rows (z = (row - zmax/dz)
+ * dz) and NR = nsamp - 2 rlo columns (column c holds R = c + 2 rlo).
+ * plane_elems is the buffer size in floats and must be at least
+ * nseries*NZ*NR. Same argument rules as fdas_search. */
+fdas_status fdas_plane(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
+                       double tsamp, double zmax, double dz, float *plane_dev,
+                       int64_t plane_elems, void *stream);
+
+/* Harmonic sums, thresholding and candidates of a caller-supplied plane in
+ * the layout fdas_plane writes (device, float32 [nseries][NZ][NR]). Output
+ * as fdas_search. Lets callers search planes they built themselves. */
+fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int32_t nseries,
+                         double tsamp, double zmax, double dz, int32_t numharm, double sigma,
+                         fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream);
+
+/* Un-normalised spectra A_k, k = 0..nsamp/2, as interleaved (re, im) float32
+ * pairs [nseries][nsamp/2+1][2] into spec_dev (device), and, if norm_host is
+ * not NULL, the normalisation of each series (float64 [nseries], host). */
+fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
+                          float *spec_dev, double *norm_host, void *stream);
+
+/* Search geometry for a series: lowest bin rlo, plane columns NR and rows NZ. */
+fdas_status fdas_geometry(int64_t nsamp, double tsamp, double zmax, double dz,
+                          const fdas_plan_opts *opts, int64_t *rlo, int64_t *nr, int32_t *nz);
+
+/* Host FP64 helpers (no device work). fdas_threshold: T_H for H = harm.
+ * fdas_sigma: Gaussian-equivalent significance of a sum of harm powers. */
+double fdas_threshold(int32_t harm, double sigma);
+double fdas_sigma(int32_t harm, double power);
+
+/* Host FP64 unit-energy template taps of a trial at r = k0 + parity/2, drift
+ * z: t_d = conj rho(parity/2 - d, z) / sqrt(E) for d = d0 .. d0 + ntaps - 1
+ * (d0 = -m + parity, m = ceil(|z|/2) + K). re/im hold cap doubles each.
+ * Returns FDAS_E_INVAL if cap is too small (*ntaps still set). */
+fdas_status fdas_template_taps(double z, int32_t parity, int32_t K, double *re, double *im,
+                               int32_t cap, int32_t *ntaps, int32_t *d0);
+
+/* What a plan chose for its current template bank: overlap-save segment
+ * length and shared half-width (each segment yields seg_len - 2 mseg valid
+ * bins), z rows, series per plane chunk and the plane workspace in bytes. */
+typedef struct {
+    int32_t seg_len;
+    int32_t mseg;
+    int32_t nz;
+    int32_t chunk_series;
+    int64_t workspace_bytes;
+} fdas_plan_info;
+fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out);
+
+/* Phase timing of a plan created with opts.profile != 0. HIP events are
+ * recorded on the search stream around every kernel phase; ms[i] receives
+ * the summed device milliseconds and launches[i] the number of timed
+ * launches of phase i since the last reset (both arrays hold FDAS_NPHASES
+ * entries, either may be NULL). Phases: 0 real FFT, 1 normalisation,
+ * 2 power plane, 3 harmonic sums, 4 compaction, 5 drift argmax, 6 copy-out.
+ * reset != 0 clears the totals after reading. */
+#define FDAS_NPHASES 7
+fdas_status fdas_profile_read(fdas_plan p, double *ms, int64_t *launches, int32_t reset);
+
+/* Description of a status code (static storage). */
+const char *fdas_status_string(fdas_status s);
+
+/* Detail of the last failure on this plan ("" if none; static if p is NULL). */
+const char *fdas_last_error(fdas_plan p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDAS_H */

@@ -1,0 +1,295 @@
+"""Python binding of the MI355X Fourier-domain acceleration search library.
+
+Argument marshalling only: every step of the search runs in the HIP kernels of
+libfdas.so (built in-tree by ``paper_1912_12807_amd.build``). PyTorch provides
+device memory and the current stream. There is no fallback: if the library
+is missing, ``load()`` raises.
+
+    import paper_1912_12807_amd as fdas
+    cands = fdas.search(x, tsamp, zmax, dz, numharm, sigma)   # x: cuda float32 [B][N]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdas.so")
+
+FDAS_OK, FDAS_E_INVAL, FDAS_E_NOMEM, FDAS_E_DEVICE, FDAS_E_TRUNC, FDAS_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+NORM_MEDIAN, NORM_FIXED = 0, 1
+
+EXPORTED = (
+    "fdas_plan_opts_default", "fdas_plan_create", "fdas_plan_destroy", "fdas_search", "fdas_plane",
+    "fdas_harmsum", "fdas_spectrum", "fdas_geometry", "fdas_threshold", "fdas_sigma",
+    "fdas_template_taps", "fdas_status_string", "fdas_last_error", "fdas_profile_read",
+    "fdas_plan_get_info",
+)
+PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "argmax", "copyout")
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("flo_hz", ctypes.c_double), ("K", ctypes.c_int32), ("norm", ctypes.c_int32),
+                ("fixed_var", ctypes.c_double), ("max_workspace_bytes", ctypes.c_int64),
+                ("max_candidates", ctypes.c_int64), ("seg_len", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("seg_len", ctypes.c_int32), ("mseg", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("chunk_series", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
+
+
+CAND_DTYPE = np.dtype([("series", "<i4"), ("harm", "<i4"), ("r_idx", "<i8"), ("z_idx", "<i4"),
+                       ("power", "<f4"), ("sigma", "<f8"), ("r_fund", "<f8"), ("z_fund", "<f8"),
+                       ("f_hz", "<f8"), ("fdot_hz_s", "<f8")], align=True)
+assert CAND_DTYPE.itemsize == 64
+
+
+class FdasError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libfdas.so (raises if it has not been built) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1912_12807_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    c = ctypes
+    P = c.c_void_p
+    lib.fdas_plan_opts_default.argtypes = [c.POINTER(PlanOpts)]
+    lib.fdas_plan_opts_default.restype = None
+    lib.fdas_plan_create.argtypes = [c.POINTER(P), c.c_int64, c.c_int32, c.c_double, c.c_double,
+                                     c.c_int32, c.POINTER(PlanOpts)]
+    lib.fdas_plan_create.restype = c.c_int
+    lib.fdas_plan_destroy.argtypes = [P]
+    lib.fdas_plan_destroy.restype = None
+    search_args = [P, P, c.c_int64, c.c_int32, c.c_double, c.c_double, c.c_double, c.c_int32,
+                   c.c_double, P, c.c_int64, c.POINTER(c.c_int64), P]
+    lib.fdas_search.argtypes = search_args
+    lib.fdas_search.restype = c.c_int
+    lib.fdas_harmsum.argtypes = search_args
+    lib.fdas_harmsum.restype = c.c_int
+    lib.fdas_plane.argtypes = [P, P, c.c_int64, c.c_int32, c.c_double, c.c_double, c.c_double, P,
+                               c.c_int64, P]
+    lib.fdas_plane.restype = c.c_int
+    lib.fdas_spectrum.argtypes = [P, P, c.c_int64, c.c_int32, P, c.POINTER(c.c_double), P]
+    lib.fdas_spectrum.restype = c.c_int
+    lib.fdas_geometry.argtypes = [c.c_int64, c.c_double, c.c_double, c.c_double, c.POINTER(PlanOpts),
+                                  c.POINTER(c.c_int64), c.POINTER(c.c_int64), c.POINTER(c.c_int32)]
+    lib.fdas_geometry.restype = c.c_int
+    lib.fdas_threshold.argtypes = [c.c_int32, c.c_double]
+    lib.fdas_threshold.restype = c.c_double
+    lib.fdas_sigma.argtypes = [c.c_int32, c.c_double]
+    lib.fdas_sigma.restype = c.c_double
+    lib.fdas_template_taps.argtypes = [c.c_double, c.c_int32, c.c_int32, c.POINTER(c.c_double),
+                                       c.POINTER(c.c_double), c.c_int32, c.POINTER(c.c_int32),
+                                       c.POINTER(c.c_int32)]
+    lib.fdas_template_taps.restype = c.c_int
+    lib.fdas_status_string.argtypes = [c.c_int]
+    lib.fdas_status_string.restype = c.c_char_p
+    lib.fdas_last_error.argtypes = [P]
+    lib.fdas_last_error.restype = c.c_char_p
+    lib.fdas_profile_read.argtypes = [P, c.POINTER(c.c_double), c.POINTER(c.c_int64), c.c_int32]
+    lib.fdas_profile_read.restype = c.c_int
+    lib.fdas_plan_get_info.argtypes = [P, c.POINTER(PlanInfo)]
+    lib.fdas_plan_get_info.restype = c.c_int
+    _lib = lib
+    return lib
+
+
+def default_opts(**kw) -> PlanOpts:
+    o = PlanOpts()
+    load().fdas_plan_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "norm" and isinstance(v, str):
+            v = {"median": NORM_MEDIAN, "fixed": NORM_FIXED}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_series(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError("series must be a CUDA float32 tensor")
+    if t.dim() == 1:
+        t = t.unsqueeze(0)
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError("series must be a contiguous [nseries][nsamp] tensor")
+    return t
+
+
+class Plan:
+    """A device plan: template bank and workspace for series up to max_nsamp."""
+
+    def __init__(self, max_nsamp: int, max_series: int, zmax: float, dz: float, numharm: int, **opts):
+        self.lib = load()
+        self.opts = default_opts(**opts)
+        self.handle = ctypes.c_void_p()
+        st = self.lib.fdas_plan_create(ctypes.byref(self.handle), int(max_nsamp), int(max_series),
+                                       float(zmax), float(dz), int(numharm), ctypes.byref(self.opts))
+        if st != FDAS_OK:
+            raise FdasError(st, f"fdas_plan_create: {self.lib.fdas_status_string(st).decode()}")
+        self.max_nsamp, self.max_series, self.zmax, self.dz, self.numharm = (
+            max_nsamp, max_series, zmax, dz, numharm)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.fdas_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st, what):
+        msg = self.lib.fdas_last_error(self.handle).decode()
+        raise FdasError(st, f"{what}: {self.lib.fdas_status_string(st).decode()}: {msg}")
+
+    def geometry(self, nsamp: int, tsamp: float, zmax: float = None, dz: float = None):
+        return geometry(nsamp, tsamp, self.zmax if zmax is None else zmax,
+                        self.dz if dz is None else dz, self.opts)
+
+    def search(self, t, tsamp: float, zmax: float = None, dz: float = None, numharm: int = None,
+               sigma: float = 6.0, cap: int = 1 << 16, stream=None, allow_trunc: bool = False):
+        """Candidates (structured numpy array, CAND_DTYPE) sorted by (series, harm, r_idx)."""
+        t = _check_series(t)
+        zmax = self.zmax if zmax is None else zmax
+        dz = self.dz if dz is None else dz
+        numharm = self.numharm if numharm is None else numharm
+        out = np.zeros(int(cap), dtype=CAND_DTYPE)
+        n = ctypes.c_int64(0)
+        st = self.lib.fdas_search(self.handle, ctypes.c_void_p(t.data_ptr()), t.shape[1], t.shape[0],
+                                  float(tsamp), float(zmax), float(dz), int(numharm), float(sigma),
+                                  out.ctypes.data_as(ctypes.c_void_p), int(cap), ctypes.byref(n),
+                                  _stream_handle(stream))
+        if st == FDAS_E_TRUNC and allow_trunc:
+            return out[:cap], int(n.value)
+        if st != FDAS_OK:
+            self._raise(st, "fdas_search")
+        return out[:n.value].copy()
+
+    def harmsum(self, plane, nsamp: int, tsamp: float, zmax: float = None, dz: float = None,
+                numharm: int = None, sigma: float = 6.0, cap: int = 1 << 16, stream=None):
+        """Candidates of a caller-built plane (CUDA float32 [B][NZ][NR])."""
+        import torch
+        if not (isinstance(plane, torch.Tensor) and plane.is_cuda and plane.dtype == torch.float32
+                and plane.is_contiguous() and plane.dim() == 3):
+            raise TypeError("plane must be a contiguous CUDA float32 [B][NZ][NR] tensor")
+        zmax = self.zmax if zmax is None else zmax
+        dz = self.dz if dz is None else dz
+        numharm = self.numharm if numharm is None else numharm
+        out = np.zeros(int(cap), dtype=CAND_DTYPE)
+        n = ctypes.c_int64(0)
+        st = self.lib.fdas_harmsum(self.handle, ctypes.c_void_p(plane.data_ptr()), int(nsamp),
+                                   plane.shape[0], float(tsamp), float(zmax), float(dz), int(numharm),
+                                   float(sigma), out.ctypes.data_as(ctypes.c_void_p), int(cap),
+                                   ctypes.byref(n), _stream_handle(stream))
+        if st != FDAS_OK:
+            self._raise(st, "fdas_harmsum")
+        return out[:n.value].copy()
+
+    def plane(self, t, tsamp: float, zmax: float = None, dz: float = None, stream=None):
+        """Normalised power plane, CUDA float32 [B][NZ][NR] (column c is R = c + 2 rlo)."""
+        import torch
+        t = _check_series(t)
+        zmax = self.zmax if zmax is None else zmax
+        dz = self.dz if dz is None else dz
+        rlo, nr, nz = self.geometry(t.shape[1], tsamp, zmax, dz)
+        out = torch.empty((t.shape[0], nz, nr), dtype=torch.float32, device=t.device)
+        st = self.lib.fdas_plane(self.handle, ctypes.c_void_p(t.data_ptr()), t.shape[1], t.shape[0],
+                                 float(tsamp), float(zmax), float(dz), ctypes.c_void_p(out.data_ptr()),
+                                 out.numel(), _stream_handle(stream))
+        if st != FDAS_OK:
+            self._raise(st, "fdas_plane")
+        return out
+
+    def info(self) -> dict:
+        """Segment length, half-width, z rows, series per chunk and workspace of the plan."""
+        i = PlanInfo()
+        self.lib.fdas_plan_get_info(self.handle, ctypes.byref(i))
+        return {k: getattr(i, k) for k, _ in PlanInfo._fields_}
+
+    def profile(self, reset: bool = False):
+        """{phase: (summed device ms, launches)} since the last reset (plans made with profile=1)."""
+        ms = (ctypes.c_double * len(PHASES))()
+        n = (ctypes.c_int64 * len(PHASES))()
+        self.lib.fdas_profile_read(self.handle, ms, n, 1 if reset else 0)
+        return {k: (ms[i], n[i]) for i, k in enumerate(PHASES)}
+
+    def spectrum(self, t, stream=None):
+        """(A, norm): CUDA complex64 [B][N/2+1] un-normalised spectra and float64 norms."""
+        import torch
+        t = _check_series(t)
+        B, N = t.shape
+        out = torch.empty((B, N // 2 + 1, 2), dtype=torch.float32, device=t.device)
+        norm = (ctypes.c_double * B)()
+        st = self.lib.fdas_spectrum(self.handle, ctypes.c_void_p(t.data_ptr()), N, B,
+                                    ctypes.c_void_p(out.data_ptr()), norm, _stream_handle(stream))
+        if st != FDAS_OK:
+            self._raise(st, "fdas_spectrum")
+        return torch.view_as_complex(out), np.array(norm[:], dtype=np.float64)
+
+
+def geometry(nsamp: int, tsamp: float, zmax: float, dz: float, opts: Optional[PlanOpts] = None):
+    """(rlo, NR, NZ) of a search."""
+    lib = load()
+    rlo, nr, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    st = lib.fdas_geometry(int(nsamp), float(tsamp), float(zmax), float(dz),
+                           ctypes.byref(opts) if opts is not None else None,
+                           ctypes.byref(rlo), ctypes.byref(nr), ctypes.byref(nz))
+    if st != FDAS_OK:
+        raise FdasError(st, f"fdas_geometry: {lib.fdas_status_string(st).decode()}")
+    return rlo.value, nr.value, nz.value
+
+
+def threshold(harm: int, sigma: float) -> float:
+    return load().fdas_threshold(int(harm), float(sigma))
+
+
+def sigma_of(harm: int, power: float) -> float:
+    return load().fdas_sigma(int(harm), float(power))
+
+
+def template_taps(z: float, parity: int, K: int = 16):
+    """(d0, taps): the library's host FP64 unit-energy taps for offsets d0, d0+1, ..."""
+    lib = load()
+    cap = 4 * (int(abs(z)) // 2 + K + 2) + 8
+    re = (ctypes.c_double * cap)()
+    im = (ctypes.c_double * cap)()
+    n, d0 = ctypes.c_int32(), ctypes.c_int32()
+    st = lib.fdas_template_taps(float(z), int(parity), int(K), re, im, cap, ctypes.byref(n), ctypes.byref(d0))
+    if st != FDAS_OK:
+        raise FdasError(st, "fdas_template_taps")
+    return d0.value, np.array(re[:n.value]) + 1j * np.array(im[:n.value])
+
+
+def search(t, tsamp: float, zmax: float, dz: float, numharm: int, sigma: float = 6.0,
+           cap: int = 1 << 16, stream=None, **opts):
+    """One-shot search of a CUDA float32 [B][N] tensor (builds a plan for it)."""
+    t = _check_series(t)
+    plan = Plan(t.shape[1], t.shape[0], zmax, dz, numharm, **opts)
+    try:
+        return plan.search(t, tsamp, zmax, dz, numharm, sigma, cap=cap, stream=stream)
+    finally:
+        plan.close()

@@ -1,0 +1,89 @@
+// Register-resident complex helpers and small DFTs (radix 2, 4, 8) for the
+// FFT kernels. DIR = -1 computes X_k = sum_n v_n exp(-2 pi i n k / R),
+// DIR = +1 the unnormalised inverse. Complex values are float2 (x = re, y = im).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fdas {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// a * (DIR i): DIR = +1 -> i a, DIR = -1 -> -i a
+template <int DIR>
+__device__ __forceinline__ float2 cmul_i(float2 a) {
+    return DIR > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// twiddle with DIR applied to a twiddle stored for DIR = +1
+template <int DIR>
+__device__ __forceinline__ float2 ctw(float2 a, float2 w) {
+    return DIR > 0 ? cmul(a, w) : cmulc(a, w);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft2(float2 &a, float2 &b) {
+    float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+// in-place 4-point DFT of (a0, a1, a2, a3)
+template <int DIR>
+__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
+    float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    float2 t2 = cadd(a1, a3), t3 = cmul_i<DIR>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+// in-place 8-point DFT of v[0..7] (natural order in and out)
+template <int DIR>
+__device__ __forceinline__ void dft8(float2 *v) {
+    constexpr float h = 0.70710678118654752440f;
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    // w8^k = exp(DIR 2 pi i k / 8)
+    float2 w1 = make_float2(h * (o1.x - DIR * o1.y), h * (o1.y + DIR * o1.x));
+    float2 w2 = cmul_i<DIR>(o2);
+    float2 w3 = make_float2(h * (-o3.x - DIR * o3.y), h * (DIR * o3.x - o3.y));
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, w1);
+    v[5] = csub(e1, w1);
+    v[2] = cadd(e2, w2);
+    v[6] = csub(e2, w2);
+    v[3] = cadd(e3, w3);
+    v[7] = csub(e3, w3);
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft_r(float2 *v) {
+    if constexpr (R == 2) {
+        dft2<DIR>(v[0], v[1]);
+    } else if constexpr (R == 4) {
+        dft4<DIR>(v[0], v[1], v[2], v[3]);
+    } else {
+        dft8<DIR>(v);
+    }
+}
+
+// exp(i pi x) for x exactly representable (x = 2 k / n with integers k, n)
+__device__ __forceinline__ float2 expipi(float x) {
+    float s, c;
+    sincospif(x, &s, &c);
+    return make_float2(c, s);
+}
+
+}  // namespace fdas

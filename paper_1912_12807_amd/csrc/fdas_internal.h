@@ -1,0 +1,90 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include "../../include/fdas.h"
+
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+#ifdef __HIPCC__
+#include <hip/hip_runtime.h>
+#else
+#include <hip/hip_runtime_api.h>
+#include <hip/hip_vector_types.h>
+#endif
+
+namespace fdas {
+
+// ---------------------------------------------------------------- host FP64 math
+std::complex<double> fresnel(double x);
+std::complex<double> response(double q, double z);
+int half_width(double z, int K);
+void unit_taps(double z, int parity, int K, std::vector<std::complex<double>> &taps, int &d0);
+void kernel_spectrum(double z, int parity, int K, int L, int mseg, float *out_interleaved);
+double log_gamma_sf(int H, double S);
+double log_gauss_tail(double s);
+double threshold(int H, double sigma);
+double sigma_of(int H, double power);
+
+// ---------------------------------------------------------------- device records
+// One thresholded column maximum, in (series, stage, column) order.
+struct DevCand {
+    int32_t b;       // series within the batch
+    int32_t s;       // stage index: H = 1 << s
+    int32_t c;       // column: R = c + 2 rlo
+    int32_t zq;      // smallest maximising z index (filled by the argmax kernel)
+    float power;     // M_H(R)
+    int32_t pad[3];
+};
+
+// ---------------------------------------------------------------- launchers
+// K1: real FFT of nseries series of n samples (n a power of two >= 8).
+// x: [nseries][n] float32; w0, w1: scratch [nseries][n/2] complex; spec: [nseries][spitch]
+// complex receiving A_k for k = 0..n/2.
+hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float2 *w1,
+                       float2 *spec, int64_t spitch, hipStream_t st);
+
+// K2: lower median of |A_k|^2 (k = 1..n/2-1) per series -> norm (FP64) and the
+// amplitude scale sqrt(1/norm) (0 when the median is 0).
+hipError_t launch_median_scale(const float2 *spec, int64_t spitch, int64_t half, int nseries,
+                               float *scale, double *norm, hipStream_t st);
+
+// K4: overlap-save correlation with the template bank and power.
+struct CorrGeom {
+    int L;            // segment length (512, 1024, 2048 or 4096)
+    int mseg;         // shared template half-width of the bank
+    int Lv;           // valid outputs per segment, L - 2 mseg
+    int nseg;         // segments per series
+    int64_t half;     // n/2
+    int64_t rlo;      // lowest searched bin
+    int NZ;           // z rows
+    int zgroups;      // z rows are split in this many groups (1, 2, 4, 8)
+};
+hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *scale,
+                             const float2 *bank, const CorrGeom &g, int nseries, float *plane,
+                             int64_t pitch, int64_t series_stride, hipStream_t st);
+
+// K5: harmonic sums and maxima over z for every column and stage.
+// maxv: [nseries][nstages][mpitch] (zero where a stage is not searched).
+hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
+                          int64_t rlo, int Z, int numharm, int nseries, float *maxv,
+                          int64_t mpitch, hipStream_t st);
+
+// K6: ordered compaction of maxv > thr[stage] into records in (b, s, c) order.
+// The batch may be processed in series chunks: state[0] (device int64) is the
+// running record count over the chunks done so far, and after the call
+// state[1] holds this chunk's first record index. Records at index >= cap are
+// counted but not written. counts/offsets: scratch of compact_blocks() entries.
+int64_t compact_blocks(int64_t nelem);
+hipError_t launch_compact(const float *maxv, int64_t nelem, int64_t mpitch, int nstages,
+                          int b0, const float *thr_dev, int32_t *counts, int64_t *offsets,
+                          int64_t *state, DevCand *out, int64_t cap, hipStream_t st);
+
+// Smallest maximising z index of this chunk's records [state[1], min(state[0], cap)),
+// recomputing the stage sums from the chunk's plane (series b0 is plane row 0).
+hipError_t launch_argmax(const float *plane, int64_t pitch, int64_t series_stride, int64_t rlo,
+                         int Z, int numharm, int b0, DevCand *rec, const int64_t *state,
+                         int64_t cap, hipStream_t st);
+
+}  // namespace fdas

@@ -1,0 +1,320 @@
+// K5: harmonic sums and their maxima over drift; K6: ordered compaction of
+// the maxima above threshold; and the argmax over drift of each candidate.
+//
+// A periodic signal puts power at harmonics k = 1..H of its fundamental
+// (r_f, z_f), i.e. at (k r_f, k z_f). Indexing a trial by its H-th harmonic
+// (R half bins, z index Zq), the k-th harmonic sits at
+//   R_k = floor((2 R k + H) / (2 H)),  Zq_k = sgn(Zq) floor((2 |Zq| k + H) / (2 H)),
+// and S_H(R, Zq) = sum_k P(R_k, Zq_k). The candidate list handed to the
+// sifting step (paper, Section 2, step 5) keeps, per stage H in 1, 2, 4, ...,
+// numharm and column R in [2 rlo H, N-1], M_H(R) = max over Zq of S_H when it
+// exceeds the stage threshold.
+//
+// Since the k-th of H harmonics equals the 2k-th of 2H, every stage is a
+// prefix of one chain over the fractions j / numharm:
+//   S_1 = P(j = nh), S_2h = S_h + sum over odd k < 2h of P(j = k nh / 2h).
+// K5 gives each lane one column R and walks Zq; the row offsets of the
+// gathers are wave-uniform (scalar), the column offsets per lane constant.
+#include "dft_small.h"
+#include "fdas_internal.h"
+
+#include <climits>
+
+namespace fdas {
+
+template <int NH>
+struct Stages {
+    static constexpr int NS = NH == 1 ? 1 : NH == 2 ? 2 : NH == 4 ? 3 : NH == 8 ? 4 : NH == 16 ? 5 : 6;
+};
+
+// Stage sums of one cell from the gathered fractions P[j - 1], j = 1..NH.
+template <int NH>
+__device__ __forceinline__ void stage_chain(const float *P, float *Ss) {
+    float S = P[NH - 1];
+    Ss[0] = S;
+    int s = 1;
+#pragma unroll
+    for (int h = 2; h <= NH; h *= 2, ++s) {
+#pragma unroll
+        for (int k = 1; k < h; k += 2) S += P[k * (NH / h) - 1];
+        Ss[s] = S;
+    }
+}
+
+// Column offsets R_j - 2 rlo and the mask of fractions some searched stage needs.
+template <int NH>
+__device__ __forceinline__ uint32_t column_offsets(int64_t R, int64_t rlo, int64_t *col) {
+    uint32_t need = 0;
+#pragma unroll
+    for (int j = 1; j <= NH; ++j) {
+        const int64_t Rj = (2 * R * j + NH) / (2 * NH);
+        col[j - 1] = Rj - 2 * rlo;
+        const int hmin = NH >> __builtin_ctz(j);     // smallest stage using fraction j
+        if (R >= 2 * rlo * hmin) need |= 1u << (j - 1);
+    }
+    return need;
+}
+
+template <int NH>
+__device__ __forceinline__ void gather(const float *__restrict__ pb, int64_t pitch, int Z, int zq,
+                                       const int64_t *col, uint32_t need, float *P) {
+    const int az = zq < 0 ? -zq : zq;
+    const int sg = zq < 0 ? -1 : 1;
+#pragma unroll
+    for (int j = 1; j <= NH; ++j) {
+        const int zj = sg * ((2 * az * j + NH) / (2 * NH));
+        P[j - 1] = (need >> (j - 1)) & 1u ? pb[(int64_t)(zj + Z) * pitch + col[j - 1]] : 0.0f;
+    }
+}
+
+template <int NH>
+__global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane, int64_t pitch,
+                                                 int64_t sstride, int64_t NR, int64_t rlo, int Z,
+                                                 float *__restrict__ maxv, int64_t mpitch) {
+    constexpr int NS = Stages<NH>::NS;
+    const int b = blockIdx.y;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= mpitch) return;
+    float *mo = maxv + (int64_t)b * NS * mpitch + c;
+    if (c >= NR) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) mo[s * mpitch] = 0.0f;
+        return;
+    }
+    const int64_t R = c + 2 * rlo;
+    int64_t col[NH];
+    const uint32_t need = column_offsets<NH>(R, rlo, col);
+    const float *pb = plane + (int64_t)b * sstride;
+    float mx[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) mx[s] = 0.0f;
+    for (int zq = -Z; zq <= Z; ++zq) {
+        float P[NH], Ss[NS];
+        gather<NH>(pb, pitch, Z, zq, col, need, P);
+        stage_chain<NH>(P, Ss);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) mx[s] = fmaxf(mx[s], Ss[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) mo[s * mpitch] = (R >= 2 * rlo * (1 << s)) ? mx[s] : 0.0f;
+}
+
+template <int NH>
+__global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ plane, int64_t pitch,
+                                                int64_t sstride, int64_t rlo, int Z, int b0,
+                                                DevCand *__restrict__ rec,
+                                                const int64_t *__restrict__ state, int64_t cap) {
+    constexpr int NS = Stages<NH>::NS;
+    const int64_t begin = state[1];
+    const int64_t end = state[0] < cap ? state[0] : cap;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t i = begin + gw; i < end; i += nw) {
+        const DevCand r = rec[i];
+        const int64_t R = r.c + 2 * rlo;
+        int64_t col[NH];
+        const uint32_t need = column_offsets<NH>(R, rlo, col);
+        const float *pb = plane + (int64_t)(r.b - b0) * sstride;
+        int best = INT_MAX;
+        for (int zq = -Z + lane; zq <= Z; zq += 64) {
+            float P[NH], Ss[NS];
+            gather<NH>(pb, pitch, Z, zq, col, need, P);
+            stage_chain<NH>(P, Ss);
+            float v = Ss[0];
+#pragma unroll
+            for (int s = 1; s < NS; ++s)
+                if (s == r.s) v = Ss[s];
+            if (v == r.power && zq < best) best = zq;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const int o = __shfl_xor(best, off, 64);
+            best = o < best ? o : best;
+        }
+        if (lane == 0) rec[i].zq = best;
+    }
+}
+
+// ------------------------------------------------------------------ compaction
+
+static constexpr int kCB = 4096;   // elements per compaction block: 256 threads x 16
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *tmp, int &total) {
+    // 256 threads: wave inclusive scans, then the wave totals
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) tmp[wid] = incl;
+    __syncthreads();
+    int base = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int x = tmp[w];
+        if (w < wid) base += x;
+        total += x;
+    }
+    __syncthreads();
+    return base + incl - v;
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_compact(const float *__restrict__ maxv, int64_t nelem,
+                                                 int64_t mpitch, int ns, int b0,
+                                                 const float *__restrict__ thr,
+                                                 int32_t *__restrict__ counts,
+                                                 const int64_t *__restrict__ offsets,
+                                                 DevCand *__restrict__ out, int64_t cap) {
+    __shared__ int tmp[4];
+    const int64_t e0 = (int64_t)blockIdx.x * kCB + (int64_t)threadIdx.x * 16;
+    float v[16];
+    int row = 0;
+    float th = INFINITY;
+    if (e0 < nelem) {
+        row = (int)(e0 / mpitch);          // mpitch is a multiple of 16: one row per thread
+        th = thr[row % ns];
+        const float4 *p = reinterpret_cast<const float4 *>(maxv + e0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float4 x = p[i];
+            v[4 * i] = x.x;
+            v[4 * i + 1] = x.y;
+            v[4 * i + 2] = x.z;
+            v[4 * i + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = 0.0f;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) cnt += v[i] > th;
+    int total;
+    const int pre = block_exclusive_scan(cnt, tmp, total);
+    if (!SCATTER) {
+        if (threadIdx.x == 0) counts[blockIdx.x] = total;
+        return;
+    }
+    if (cnt == 0) return;
+    int64_t o = offsets[blockIdx.x] + pre;
+    const int64_t c0 = e0 - (int64_t)row * mpitch;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (v[i] > th) {
+            if (o < cap) {
+                DevCand d;
+                d.b = b0 + row / ns;
+                d.s = row % ns;
+                d.c = (int32_t)(c0 + i);
+                d.zq = INT_MAX;
+                d.power = v[i];
+                d.pad[0] = d.pad[1] = d.pad[2] = 0;
+                out[o] = d;
+            }
+            ++o;
+        }
+    }
+}
+
+// Exclusive scan of the block counts, offset by the running total in state[0].
+__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict__ counts,
+                                                      int64_t nblk, int64_t *__restrict__ offsets,
+                                                      int64_t *__restrict__ state) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nblk + 1023) / 1024;
+    const int64_t lo = t * per;
+    const int64_t hi = lo + per < nblk ? lo + per : nblk;
+    int64_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += counts[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t x = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    const int64_t base0 = state[0];
+    int64_t run = base0 + part[t] - sum;
+    for (int64_t i = lo; i < hi; ++i) {
+        offsets[i] = run;
+        run += counts[i];
+    }
+    __syncthreads();
+    if (t == 0) {
+        state[1] = base0;
+        state[0] = base0 + part[1023];
+    }
+}
+
+template <int NH>
+static void launch_harm_nh(const float *plane, int64_t pitch, int64_t sstride, int64_t NR,
+                           int64_t rlo, int Z, int nseries, float *maxv, int64_t mpitch,
+                           hipStream_t st) {
+    dim3 grid((unsigned)((mpitch + 255) / 256), (unsigned)nseries);
+    hipLaunchKernelGGL(k_harmsum<NH>, grid, dim3(256), 0, st, plane, pitch, sstride, NR, rlo, Z,
+                       maxv, mpitch);
+}
+
+hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
+                          int64_t rlo, int Z, int numharm, int nseries, float *maxv,
+                          int64_t mpitch, hipStream_t st) {
+    if (nseries < 1 || nseries > 65535 || mpitch < NR || (mpitch & 15)) return hipErrorInvalidValue;
+    switch (numharm) {
+    case 1: launch_harm_nh<1>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
+    case 2: launch_harm_nh<2>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
+    case 4: launch_harm_nh<4>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
+    case 8: launch_harm_nh<8>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
+    case 16: launch_harm_nh<16>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
+    case 32: launch_harm_nh<32>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int64_t compact_blocks(int64_t nelem) { return (nelem + kCB - 1) / kCB; }
+
+hipError_t launch_compact(const float *maxv, int64_t nelem, int64_t mpitch, int nstages, int b0,
+                          const float *thr_dev, int32_t *counts, int64_t *offsets, int64_t *state,
+                          DevCand *out, int64_t cap, hipStream_t st) {
+    if ((mpitch & 15) || nelem % mpitch) return hipErrorInvalidValue;
+    const int64_t nblk = compact_blocks(nelem);
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_compact<false>, dim3((unsigned)nblk), dim3(256), 0, st, maxv, nelem, mpitch,
+                       nstages, b0, thr_dev, counts, offsets, out, cap);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, counts, nblk, offsets, state);
+    hipLaunchKernelGGL(k_compact<true>, dim3((unsigned)nblk), dim3(256), 0, st, maxv, nelem, mpitch,
+                       nstages, b0, thr_dev, counts, offsets, out, cap);
+    return hipGetLastError();
+}
+
+template <int NH>
+static void launch_argmax_nh(const float *plane, int64_t pitch, int64_t sstride, int64_t rlo,
+                             int Z, int b0, DevCand *rec, const int64_t *state, int64_t cap,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_argmax<NH>, dim3(1024), dim3(256), 0, st, plane, pitch, sstride, rlo, Z, b0,
+                       rec, state, cap);
+}
+
+hipError_t launch_argmax(const float *plane, int64_t pitch, int64_t series_stride, int64_t rlo,
+                         int Z, int numharm, int b0, DevCand *rec, const int64_t *state,
+                         int64_t cap, hipStream_t st) {
+    switch (numharm) {
+    case 1: launch_argmax_nh<1>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
+    case 2: launch_argmax_nh<2>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
+    case 4: launch_argmax_nh<4>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
+    case 8: launch_argmax_nh<8>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
+    case 16: launch_argmax_nh<16>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
+    case 32: launch_argmax_nh<32>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fdas

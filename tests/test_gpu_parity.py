@@ -1,0 +1,233 @@
+"""HIP path versus the FP64 oracle at sizes the oracle finishes in seconds.
+
+Every case spans several overlap-save segments and harmonic-sum tiles and
+ends in a ragged tail (the last segment and tile are partial).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from fdas_check import OracleSeries, assert_candidates_match, assert_plane_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _noise(B, N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((B, N)).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------- spectrum
+
+@pytest.mark.parametrize("N", [8, 64, 1 << 12, 1 << 17])
+def test_spectrum_and_median_norm(fdas_gpu, N):
+    B = 3
+    x = _noise(B, N, N)
+    x[1] *= 5.0
+    plan = fdas_gpu.Plan(N, B, 0.0, 2.0, 1, flo_hz=0.0)
+    A, norm = plan.spectrum(_cuda(x))
+    A = A.cpu().numpy().astype(np.complex128)
+    for b in range(B):
+        ref = O.spectrum(x[b])
+        err = np.max(np.abs(A[b] - ref)) / np.max(np.abs(ref))
+        assert err < 3e-6, (b, err)
+        _, nref = O.normalise(ref)
+        assert norm[b] == pytest.approx(nref, rel=2e-5)
+
+
+# ----------------------------------------------------------------------------- plane
+
+PLANE_CASES = [
+    # (N, tsamp, zmax, dz, K, seg_len)
+    (1 << 12, 1e-3, 0.0, 2.0, 16, 0),        # one z row, L = 512
+    (1 << 13, 1e-3, 10.0, 2.0, 16, 0),       # L = 512, many segments
+    (1 << 13, 1e-3, 10.0, 2.0, 8, 1024),     # forced L = 1024, other K
+    (1 << 14, 1e-3, 40.0, 1.0, 16, 0),       # 81 rows, L = 1024, four z groups
+    (1 << 14, 1e-3, 200.0, 2.0, 16, 0),      # 201 rows, L = 2048, eight z groups
+    (1 << 14, 1e-3, 300.0, 4.0, 16, 0),      # L = 4096
+]
+
+
+@pytest.mark.parametrize("case", PLANE_CASES, ids=lambda c: f"N{c[0]}-z{c[2]}-dz{c[3]}-K{c[4]}-L{c[5]}")
+def test_plane_matches_oracle(fdas_gpu, case):
+    N, ts, zmax, dz, K, L = case
+    B = 2
+    wl = synth.small_batch(B, N, ts, zmax, dz, 1, config=92, signals=2, amp_range=(0.2, 0.6))
+    x = synth.generate(wl)
+    plan = fdas_gpu.Plan(N, B, zmax, dz, 1, K=K, seg_len=L)
+    P = plan.plane(_cuda(x), ts).cpu().numpy()
+    rlo = O.rlo_bins(N, ts)
+    for b in range(B):
+        Ah, _ = O.normalise(O.spectrum(x[b]))
+        ref = O.plane(Ah, rlo, zmax, dz, K, method="fft")
+        assert_plane_close(P[b], ref)
+
+
+def test_plane_single_series_workload(fdas_gpu):
+    wl = synth.config1()
+    x = synth.generate(wl)
+    plan = fdas_gpu.Plan(wl.nsamp, 1, wl.zmax, wl.dz, 1)
+    P = plan.plane(_cuda(x), wl.tsamp).cpu().numpy()[0]
+    Ah, _ = O.normalise(O.spectrum(x[0]))
+    ref = O.plane(Ah, O.rlo_bins(wl.nsamp, wl.tsamp), wl.zmax, wl.dz, method="direct")
+    assert_plane_close(P, ref)
+
+
+def test_plane_fixed_norm_noise_free_peak(fdas_gpu):
+    wl = synth.config1(noise=False)
+    x = synth.generate(wl)
+    plan = fdas_gpu.Plan(wl.nsamp, 1, wl.zmax, wl.dz, 1, norm="fixed", fixed_var=1.0)
+    P = plan.plane(_cuda(x), wl.tsamp).cpu().numpy()[0]
+    rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
+    # grid maximum of the injected sinusoid at (r, z) = (10000.5, 8)
+    zi, c = np.unravel_index(np.argmax(P), P.shape)
+    assert (zi - 10, c + 2 * rlo) == (4, 20001)
+    assert P[zi, c] == pytest.approx(70.258485, rel=1e-4)
+
+
+# ----------------------------------------------------------------------------- harmonic sums
+
+@pytest.mark.parametrize("numharm", [1, 2, 4, 8, 16, 32])
+def test_harmsum_bit_exact_on_integer_planes(fdas_gpu, numharm):
+    import torch
+    B, N, ts, zmax, dz = 3, 1 << 12, 1e-2, 6.0, 2.0
+    rlo = O.rlo_bins(N, ts)
+    Z = O.z_index_max(zmax, dz)
+    rng = np.random.default_rng(100 + numharm)
+    planes = rng.integers(0, 40, size=(B, 2 * Z + 1, N - 2 * rlo)).astype(np.float32)
+    # a few strong integer peaks so that high stages pass their thresholds too
+    for b in range(B):
+        for _ in range(20):
+            planes[b, rng.integers(0, 2 * Z + 1), rng.integers(0, N - 2 * rlo)] = rng.integers(100, 4000)
+    sigma = 6.0
+    plan = fdas_gpu.Plan(N, B, zmax, dz, numharm)
+    g = plan.harmsum(torch.from_numpy(planes).cuda(), N, ts, sigma=sigma, cap=1 << 18)
+    got = sorted((int(c["series"]), int(c["harm"]), int(c["r_idx"]), int(c["z_idx"]), float(c["power"]))
+                 for c in g)
+    ref = []
+    for b in range(B):
+        orc = OracleSeries(np.zeros(N), ts, zmax, dz, numharm, plane=planes[b])
+        for H, R, Zq, M in orc.candidates(sigma):
+            ref.append((b, H, R, Zq, M))
+    ref.sort()
+    assert len(ref) > 100
+    assert got == ref
+
+
+# ----------------------------------------------------------------------------- search
+
+def test_search_single_series_workload(fdas_gpu):
+    wl = synth.config1()
+    x = synth.generate(wl)
+    plan = fdas_gpu.Plan(wl.nsamp, 1, wl.zmax, wl.dz, wl.numharm)
+    g = plan.search(_cuda(x), wl.tsamp, sigma=wl.sigma)
+    orc = OracleSeries(x[0], wl.tsamp, wl.zmax, wl.dz, wl.numharm, method="direct")
+    common, _ = assert_candidates_match(g, {0: orc}, wl.sigma)
+    assert common >= 1
+    best = g[np.argmax(g["power"])]
+    assert abs(best["r_fund"] - 10000.3) <= 1.0 and abs(best["z_fund"] - 7.5) <= 2.0
+
+
+def test_search_noise_free_fixed_norm_three_candidates(fdas_gpu):
+    wl = synth.config1(noise=False)
+    x = synth.generate(wl)
+    plan = fdas_gpu.Plan(wl.nsamp, 1, wl.zmax, wl.dz, 1, norm="fixed", fixed_var=1.0)
+    g = plan.search(_cuda(x), wl.tsamp, sigma=6.0)
+    assert [(int(c["r_idx"]), int(c["z_idx"])) for c in g] == [(20000, 4), (20001, 4), (20003, 1)]
+    assert g["power"][1] == pytest.approx(70.258485, rel=1e-4)
+    assert g["sigma"][1] == pytest.approx(O.candidate_sigma(1, g["power"][1]), rel=1e-9)
+    assert g["f_hz"][1] == pytest.approx(10000.5 / (wl.nsamp * wl.tsamp), rel=1e-12)
+    assert g["fdot_hz_s"][1] == pytest.approx(8.0 / (wl.nsamp * wl.tsamp) ** 2, rel=1e-12)
+
+
+SEARCH_CASES = [
+    # (B, N, tsamp, zmax, dz, numharm, sigma)
+    (4, 1 << 14, 1e-3, 20.0, 2.0, 4, 6.0),
+    (3, 1 << 15, 5e-4, 50.0, 2.0, 8, 6.0),
+    (2, 1 << 14, 1e-3, 200.0, 2.0, 16, 5.0),
+    (2, 1 << 13, 2e-3, 10.0, 1.0, 32, 4.0),
+    (2, 1 << 13, 1e-3, 0.0, 2.0, 8, 3.0),
+]
+
+
+@pytest.mark.parametrize("case", SEARCH_CASES, ids=lambda c: f"B{c[0]}-N{c[1]}-z{c[3]}-h{c[5]}-s{c[6]}")
+def test_search_matches_oracle(fdas_gpu, case):
+    B, N, ts, zmax, dz, nh, sigma = case
+    wl = synth.small_batch(B, N, ts, zmax, dz, nh, sigma=sigma, config=93, signals=B,
+                           amp_range=(0.3, 1.0))
+    x = synth.generate(wl)
+    plan = fdas_gpu.Plan(N, B, zmax, dz, nh)
+    g = plan.search(_cuda(x), ts, sigma=sigma, cap=1 << 18)
+    oracles = {b: OracleSeries(x[b], ts, zmax, dz, nh, method="fft") for b in range(B)}
+    common, banded = assert_candidates_match(g, oracles, sigma)
+    assert common >= 1
+
+
+def test_search_chunked_workspace_matches_unchunked(fdas_gpu):
+    B, N, ts, zmax, dz, nh = 5, 1 << 13, 1e-3, 20.0, 2.0, 4
+    wl = synth.small_batch(B, N, ts, zmax, dz, nh, config=94, signals=3)
+    x = _cuda(synth.generate(wl))
+    full = fdas_gpu.Plan(N, B, zmax, dz, nh).search(x, ts, sigma=4.0, cap=1 << 18)
+    rows = 2 * O.z_index_max(zmax, dz) + 1
+    small = fdas_gpu.Plan(N, B, zmax, dz, nh, max_workspace_bytes=2 * rows * N * 4,
+                          max_candidates=64).search(x, ts, sigma=4.0, cap=1 << 18)
+    assert len(full) > 64
+    assert np.array_equal(full, small)
+
+
+# ----------------------------------------------------------------------------- edge cases
+
+def test_zero_series_give_no_candidates(fdas_gpu):
+    N = 1 << 12
+    x = np.zeros((2, N), dtype=np.float32)
+    x[1] = _noise(1, N, 5)[0]
+    plan = fdas_gpu.Plan(N, 2, 10.0, 2.0, 4)
+    g = plan.search(_cuda(x), 1e-3, sigma=3.0)
+    assert not np.any(g["series"] == 0)
+
+
+def test_truncation_reports_true_count(fdas_gpu):
+    N = 1 << 13
+    x = _noise(2, N, 7)
+    plan = fdas_gpu.Plan(N, 2, 10.0, 2.0, 2)
+    full = plan.search(_cuda(x), 1e-3, sigma=2.0, cap=1 << 16)
+    assert len(full) > 50
+    part, total = plan.search(_cuda(x), 1e-3, sigma=2.0, cap=17, allow_trunc=True)
+    assert total == len(full)
+    assert np.array_equal(part, full[:17])
+
+
+def test_invalid_arguments_return_status(fdas_gpu):
+    F = fdas_gpu
+    N = 1 << 12
+    x = _cuda(_noise(2, N, 9))
+    plan = F.Plan(N, 2, 10.0, 2.0, 4)
+    bad = [dict(zmax=11.0), dict(numharm=8), dict(numharm=3), dict(sigma=0.0), dict(sigma=float("nan")),
+           dict(tsamp=0.0), dict(tsamp=10.0)]
+    for kw in bad:
+        args = dict(tsamp=1e-3, zmax=10.0, dz=2.0, numharm=4, sigma=6.0)
+        args.update(kw)
+        with pytest.raises(F.FdasError) as e:
+            plan.search(x, **args)
+        assert e.value.status == F.FDAS_E_INVAL, kw
+    big = _cuda(_noise(1, 2 * N, 1))
+    with pytest.raises(F.FdasError) as e:
+        plan.search(big, 1e-3)
+    assert e.value.status == F.FDAS_E_INVAL
+    with pytest.raises(F.FdasError) as e:
+        plan.search(_cuda(_noise(3, N, 1)), 1e-3)
+    assert e.value.status == F.FDAS_E_INVAL
+    odd = F.Plan(N, 2, 10.0, 2.0, 4)
+    with pytest.raises(F.FdasError) as e:
+        odd.search(_cuda(_noise(1, N - 24, 1)), 1e-3)
+    assert e.value.status == F.FDAS_E_UNSUPPORTED
+    # the plan still works after rejected calls
+    assert plan.search(x, 1e-3, sigma=6.0) is not None
