@@ -60,7 +60,10 @@ typedef struct {
     int64_t max_candidates;      /* initial device candidate capacity (0 = 1<<20) */
     int32_t seg_len;             /* overlap-save segment length L, 512..4096 (0 = automatic) */
     int32_t profile;             /* nonzero: time every phase with HIP events (fdas_profile_read) */
-    int32_t reserved[6];         /* must be zero */
+    int32_t harm_order;          /* harmonic-sum tile order: 0 automatic, 1 each XCD sweeps its own
+                                    series, 2 all XCDs sweep one series at a time, 3 as 2 in two
+                                    drift halves (results never depend on it) */
+    int32_t reserved[5];         /* must be zero */
 } fdas_plan_opts;
 
 /* One candidate. r = r_idx/2 and z = z_idx*dz are the Fourier frequency

@@ -152,6 +152,7 @@ def normalise(A: np.ndarray, mode: str = "median", fixed_var: float = 1.0):
             M = N/2 - 1 bins k = 1..N/2-1 (the lower median; the median of a
             unit exponential is ln 2, so white noise maps to unit mean power);
     fixed : norm = N * fixed_var (the exact mean of |A_k|^2 for white noise).
+    A median of zero (e.g. an all-zero series) leaves all powers at zero.
     """
     A = np.asarray(A, dtype=np.complex128)
     half = A.shape[-1] - 1            # N/2
@@ -164,6 +165,9 @@ def normalise(A: np.ndarray, mode: str = "median", fixed_var: float = 1.0):
         norm = float(N) * float(fixed_var)
     else:
         raise ValueError(mode)
+    if norm <= 0.0:
+        # a series whose median power is zero carries no searchable power
+        return np.zeros_like(A), norm
     Ah = A / math.sqrt(norm)
     Ah[0] = 0.0
     Ah[half] = 0.0
@@ -229,23 +233,30 @@ def plane(Ah: np.ndarray, rlo: int, zmax: float, dz: float, K: int = 16,
 
 def plane_cells(Ah: np.ndarray, R: Sequence[int], Zq: Sequence[int], dz: float,
                 K: int = 16) -> np.ndarray:
-    """P at the listed cells (R half bins, Zq z-steps), each by its own direct tap sum."""
+    """P at the listed cells (R half bins, Zq z-steps), each by its own direct tap sum.
+
+    Cells sharing a template (same Zq and parity) are evaluated together; every
+    cell is still the plain sum over its own taps.
+    """
     R = np.asarray(R, dtype=np.int64)
     Zq = np.asarray(Zq, dtype=np.int64)
     out = np.empty(R.shape[0], dtype=np.float64)
     half = Ah.shape[-1] - 1
-    cache: Dict = {}
-    for i in range(R.shape[0]):
-        z = float(Zq[i]) * dz
-        p = int(R[i] & 1)
-        key = (int(Zq[i]), p)
-        if key not in cache:
-            cache[key] = template(z, p, K)
-        d, t = cache[key]
-        k = (R[i] >> 1) + d
+    if R.shape[0] == 0:
+        return out
+    key = Zq * 2 + (R & 1)
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    bounds = np.nonzero(np.diff(ks))[0] + 1
+    for grp in np.split(order, bounds):
+        z = float(Zq[grp[0]]) * dz
+        p = int(R[grp[0]] & 1)
+        d, t = template(z, p, K)
+        k = (R[grp] >> 1)[:, None] + d[None, :]
         ok = (k >= 1) & (k <= half - 1)
-        c = np.sum(Ah[k[ok]] * t[ok])
-        out[i] = c.real ** 2 + c.imag ** 2
+        vals = np.where(ok, Ah[np.clip(k, 0, half)], 0.0)
+        c = np.sum(vals * t[None, :], axis=1)
+        out[grp] = c.real ** 2 + c.imag ** 2
     return out
 
 
@@ -388,30 +399,29 @@ def search(batch, tsamp: float, zmax: float, dz: float, numharm: int, sigma: flo
 
 
 def window_maxima(Ah: np.ndarray, rlo: int, zmax: float, dz: float, H: int, R_lo: int,
-                  R_hi: int, K: int = 16):
-    """M_H(R), Zq* for R in [R_lo, R_hi) from directly evaluated plane cells only.
+                  R_hi: int, K: int = 16, R_list: Optional[Sequence[int]] = None):
+    """M_H(R), Zq* (and all S_H) for R in [R_lo, R_hi) (or the listed R) from directly
+    evaluated plane cells only.
 
-    Evaluates just the cells the H-harmonic sums of that window read, so it
+    Evaluates just the cells the H-harmonic sums of those columns read, so it
     works at any series length.
     """
     Z = z_index_max(zmax, dz)
-    R = np.arange(R_lo, R_hi, dtype=np.int64)
+    R = np.arange(R_lo, R_hi, dtype=np.int64) if R_list is None else np.asarray(R_list, dtype=np.int64)
     Zq = np.arange(-Z, Z + 1, dtype=np.int64)
-    need = set()
+    cellsR, cellsZ = [], []
     for k in range(1, H + 1):
         Rk, _ = harmonic_index(R, 0, k, H)
         _, Zk = harmonic_index(0, Zq, k, H)
-        for zz in np.unique(Zk):
-            for rr in np.unique(Rk):
-                need.add((int(rr), int(zz)))
-    cells = sorted(need)
-    vals = plane_cells(Ah, [c[0] for c in cells], [c[1] for c in cells], dz, K)
-    lut = {c: v for c, v in zip(cells, vals)}
+        cellsR.append(np.repeat(Rk[None, :], Zq.shape[0], axis=0).ravel())
+        cellsZ.append(np.repeat(Zk[:, None], R.shape[0], axis=1).ravel())
+    cR = np.concatenate(cellsR)
+    cZ = np.concatenate(cellsZ)
+    uniq, inv = np.unique(np.stack([cR, cZ], axis=1), axis=0, return_inverse=True)
+    vals = plane_cells(Ah, uniq[:, 0], uniq[:, 1], dz, K)[inv.ravel()]
+    n = Zq.shape[0] * R.shape[0]
     S = np.zeros((Zq.shape[0], R.shape[0]), dtype=np.float64)
-    for k in range(1, H + 1):
-        Rk, _ = harmonic_index(R, 0, k, H)
-        _, Zk = harmonic_index(0, Zq, k, H)
-        for a, zz in enumerate(Zk):
-            S[a] += np.array([lut[(int(rr), int(zz))] for rr in Rk])
+    for k in range(H):
+        S += vals[k * n:(k + 1) * n].reshape(Zq.shape[0], R.shape[0])
     a = np.argmax(S, axis=0)
     return R, S[a, np.arange(R.shape[0])], a - Z, S

@@ -35,7 +35,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("flo_hz", ctypes.c_double), ("K", ctypes.c_int32), ("norm", ctypes.c_int32),
                 ("fixed_var", ctypes.c_double), ("max_workspace_bytes", ctypes.c_int64),
                 ("max_candidates", ctypes.c_int64), ("seg_len", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("profile", ctypes.c_int32), ("harm_order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class PlanInfo(ctypes.Structure):

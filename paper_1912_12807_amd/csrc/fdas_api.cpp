@@ -302,7 +302,8 @@ fdas_status run_harm_chunk(fdas_plan p, const float *plane, int64_t pitch, int64
     const int NS = nstages_of(numharm);
     const int64_t mpitch = round_up(g.NR, 16);
     hipEvent_t e = p->begin(st);
-    HIPTRY(p, launch_harmsum(plane, pitch, sstride, g.NR, g.rlo, g.Z, numharm, nb, p->d_maxv, mpitch, st));
+    const int order = p->opts.harm_order ? p->opts.harm_order : 1;
+    HIPTRY(p, launch_harmsum(plane, pitch, sstride, g.NR, g.rlo, g.Z, numharm, nb, p->d_maxv, mpitch, order, st));
     p->end(3, e, st);
     const int64_t nelem = (int64_t)nb * NS * mpitch;
     e = p->begin(st);
@@ -452,12 +453,12 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     fdas_plan_opts o;
     fdas_plan_opts_default(&o);
     if (opts) o = *opts;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
         if (o.reserved[i]) return FDAS_E_INVAL;
     if (max_series < 1 || max_series > 65535 || !valid_numharm(numharm) || o.K < 1 || o.K > 1024 ||
         (o.norm != FDAS_NORM_MEDIAN && o.norm != FDAS_NORM_FIXED) ||
         (o.norm == FDAS_NORM_FIXED && !(o.fixed_var > 0)) || o.max_workspace_bytes < 0 ||
-        o.max_candidates < 0)
+        o.max_candidates < 0 || o.harm_order < 0 || o.harm_order > 3)
         return FDAS_E_INVAL;
     Geometry g;
     if (geometry(max_nsamp, 1e-3, zmax, dz, 0.0, g) != FDAS_OK) return FDAS_E_INVAL;

@@ -67,9 +67,12 @@ hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *sc
 
 // K5: harmonic sums and maxima over z for every column and stage.
 // maxv: [nseries][nstages][mpitch] (zero where a stage is not searched).
+// order: 1 each XCD sweeps a contiguous run of tiles, 2 all XCDs sweep the
+// tiles in launch order, 3 as 2 but in two launches over the drift halves
+// (Zq <= 0, then Zq > 0 merged), which halves the live plane per series.
 hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
                           int64_t rlo, int Z, int numharm, int nseries, float *maxv,
-                          int64_t mpitch, hipStream_t st);
+                          int64_t mpitch, int order, hipStream_t st);
 
 // K6: ordered compaction of maxv > thr[stage] into records in (b, s, c) order.
 // The batch may be processed in series chunks: state[0] (device int64) is the

@@ -67,13 +67,37 @@ __device__ __forceinline__ void gather(const float *__restrict__ pb, int64_t pit
     }
 }
 
+// Row of fraction j for drift index zq (wave-uniform).
+template <int NH>
+__device__ __forceinline__ int frac_row(int zq, int j) {
+    const int az = zq < 0 ? -zq : zq;
+    const int r = (2 * az * j + NH) / (2 * NH);
+    return zq < 0 ? -r : r;
+}
+
+// One lane per column R. As Zq sweeps -Z..Z, the row of fraction j changes
+// only every ~NH/j steps, so each fraction's value stays in a register and is
+// reloaded only when its (wave-uniform) row changes: about (NH+1)/2 loads per
+// cell instead of NH. The next sweep step's loads are issued before the
+// current step is summed. Column tiles are assigned so that each XCD (workgroup
+// id mod 8) works through a contiguous run of tiles of one series, whose
+// fraction strips overlap in its L2.
 template <int NH>
 __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane, int64_t pitch,
                                                  int64_t sstride, int64_t NR, int64_t rlo, int Z,
-                                                 float *__restrict__ maxv, int64_t mpitch) {
+                                                 float *__restrict__ maxv, int64_t mpitch,
+                                                 int64_t tiles_per_series, int64_t total_tiles,
+                                                 int xcd_runs, int zq_lo, int zq_hi, int merge) {
     constexpr int NS = Stages<NH>::NS;
-    const int b = blockIdx.y;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t w = blockIdx.x;
+    int64_t g = w;
+    if (xcd_runs) {
+        const int64_t per_xcd = (total_tiles + 7) / 8;
+        g = (w & 7) * per_xcd + (w >> 3);
+    }
+    if (g >= total_tiles) return;
+    const int b = (int)(g / tiles_per_series);
+    const int64_t c = (g - (int64_t)b * tiles_per_series) * 256 + threadIdx.x;
     if (c >= mpitch) return;
     float *mo = maxv + (int64_t)b * NS * mpitch + c;
     if (c >= NR) {
@@ -84,16 +108,42 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
     const int64_t R = c + 2 * rlo;
     int64_t col[NH];
     const uint32_t need = column_offsets<NH>(R, rlo, col);
-    const float *pb = plane + (int64_t)b * sstride;
+    const float *pb = plane + (int64_t)b * sstride + (int64_t)Z * pitch;   // row Zq = 0
     float mx[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) mx[s] = 0.0f;
-    for (int zq = -Z; zq <= Z; ++zq) {
-        float P[NH], Ss[NS];
-        gather<NH>(pb, pitch, Z, zq, col, need, P);
-        stage_chain<NH>(P, Ss);
+
+    if (merge) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) mx[s] = mo[s * mpitch];
+    }
+    float cur[NH];
+    int row[NH];
+#pragma unroll
+    for (int j = 1; j <= NH; ++j) {
+        row[j - 1] = frac_row<NH>(zq_lo, j);
+        cur[j - 1] = (need >> (j - 1)) & 1u ? pb[(int64_t)row[j - 1] * pitch + col[j - 1]] : 0.0f;
+    }
+    for (int zq = zq_lo; zq <= zq_hi; ++zq) {
+        float nxt[NH];
+#pragma unroll
+        for (int j = 1; j <= NH; ++j) nxt[j - 1] = cur[j - 1];
+        if (zq < zq_hi) {
+#pragma unroll
+            for (int j = 1; j <= NH; ++j) {
+                const int r = frac_row<NH>(zq + 1, j);
+                if (r != row[j - 1]) {
+                    row[j - 1] = r;
+                    nxt[j - 1] = (need >> (j - 1)) & 1u ? pb[(int64_t)r * pitch + col[j - 1]] : 0.0f;
+                }
+            }
+        }
+        float Ss[NS];
+        stage_chain<NH>(cur, Ss);
 #pragma unroll
         for (int s = 0; s < NS; ++s) mx[s] = fmaxf(mx[s], Ss[s]);
+#pragma unroll
+        for (int j = 0; j < NH; ++j) cur[j] = nxt[j];
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) mo[s * mpitch] = (R >= 2 * rlo * (1 << s)) ? mx[s] : 0.0f;
@@ -255,24 +305,37 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict_
 
 template <int NH>
 static void launch_harm_nh(const float *plane, int64_t pitch, int64_t sstride, int64_t NR,
-                           int64_t rlo, int Z, int nseries, float *maxv, int64_t mpitch,
+                           int64_t rlo, int Z, int nseries, float *maxv, int64_t mpitch, int order,
                            hipStream_t st) {
-    dim3 grid((unsigned)((mpitch + 255) / 256), (unsigned)nseries);
-    hipLaunchKernelGGL(k_harmsum<NH>, grid, dim3(256), 0, st, plane, pitch, sstride, NR, rlo, Z,
-                       maxv, mpitch);
+    const int64_t tps = (mpitch + 255) / 256;
+    const int64_t total = tps * nseries;
+    const int64_t nwg = 8 * ((total + 7) / 8);
+    const int xcd_runs = order == 1 ? 1 : 0;
+    if (order == 3 && Z > 0) {
+        // negative drift half, then the positive half merged into the same maxima
+        hipLaunchKernelGGL(k_harmsum<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
+                           NR, rlo, Z, maxv, mpitch, tps, total, 0, -Z, 0, 0);
+        hipLaunchKernelGGL(k_harmsum<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
+                           NR, rlo, Z, maxv, mpitch, tps, total, 0, 1, Z, 1);
+    } else {
+        hipLaunchKernelGGL(k_harmsum<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
+                           NR, rlo, Z, maxv, mpitch, tps, total, xcd_runs, -Z, Z, 0);
+    }
 }
 
 hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
                           int64_t rlo, int Z, int numharm, int nseries, float *maxv,
-                          int64_t mpitch, hipStream_t st) {
-    if (nseries < 1 || nseries > 65535 || mpitch < NR || (mpitch & 15)) return hipErrorInvalidValue;
+                          int64_t mpitch, int order, hipStream_t st) {
+    if (nseries < 1 || mpitch < NR || (mpitch & 15) || (mpitch + 255) / 256 * nseries > 0x7ffffff0LL ||
+        order < 1 || order > 3)
+        return hipErrorInvalidValue;
     switch (numharm) {
-    case 1: launch_harm_nh<1>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
-    case 2: launch_harm_nh<2>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
-    case 4: launch_harm_nh<4>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
-    case 8: launch_harm_nh<8>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
-    case 16: launch_harm_nh<16>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
-    case 32: launch_harm_nh<32>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, st); break;
+    case 1: launch_harm_nh<1>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
+    case 2: launch_harm_nh<2>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
+    case 4: launch_harm_nh<4>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
+    case 8: launch_harm_nh<8>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
+    case 16: launch_harm_nh<16>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
+    case 32: launch_harm_nh<32>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1,0 +1,189 @@
+"""HIP path versus the oracle at the full workload sizes.
+
+The batch is searched exactly as the benchmark does (same plan options, one
+launch per kernel). The oracle checks what it can compute at these sizes:
+complete candidate lists of selected series (FFT-convolution oracle), every
+GPU candidate by directly evaluated plane cells, random non-candidate columns,
+sampled plane cells, and recovery of the injected signals.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from fdas_check import OracleSeries, assert_candidates_match
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-4
+_SPEC = {}
+
+
+def _ah(key, x):
+    """Normalised FP64 oracle spectrum, cached per series."""
+    if key not in _SPEC:
+        _SPEC[key] = O.normalise(O.spectrum(x))[0]
+    return _SPEC[key]
+
+
+def _verify_candidates(cands, x_of, wl, max_check=None, seed=0):
+    """Every listed GPU candidate against directly evaluated oracle sums of its column."""
+    rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
+    by = {}
+    for c in cands:
+        by.setdefault((int(c["series"]), int(c["harm"])), []).append(c)
+    rng = np.random.default_rng(seed)
+    checked = 0
+    for (b, H), lst in sorted(by.items()):
+        if max_check is not None and len(lst) > max_check:
+            lst = [lst[i] for i in sorted(rng.choice(len(lst), max_check, replace=False))]
+        Ah = _ah((wl.name, b), x_of(b))
+        R = [int(c["r_idx"]) for c in lst]
+        _, M, Zs, S = O.window_maxima(Ah, rlo, wl.zmax, wl.dz, H, 0, 0, R_list=R)
+        T = O.threshold(H, wl.sigma)
+        for i, c in enumerate(lst):
+            assert M[i] > T * (1 - REL), (b, H, R[i], M[i], T)
+            assert abs(float(c["power"]) - M[i]) <= REL * max(M[i], 1.0), (b, H, R[i], c["power"], M[i])
+            zg = int(c["z_idx"])
+            if zg != Zs[i]:
+                assert S[zg + O.z_index_max(wl.zmax, wl.dz), i] >= M[i] * (1 - REL)
+            checked += 1
+    return checked
+
+
+def _non_candidates(cands, x_of, wl, series, n=40, seed=1):
+    """Random columns the GPU did not report must not exceed the threshold in the oracle."""
+    rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
+    rng = np.random.default_rng(seed)
+    have = {(int(c["series"]), int(c["harm"]), int(c["r_idx"])) for c in cands}
+    for b in series:
+        Ah = _ah((wl.name, b), x_of(b))
+        for H in O.stage_list(wl.numharm):
+            R = rng.integers(2 * rlo * H, wl.nsamp, n)
+            R = [int(r) for r in R if (b, H, int(r)) not in have]
+            _, M, _, _ = O.window_maxima(Ah, rlo, wl.zmax, wl.dz, H, 0, 0, R_list=R)
+            T = O.threshold(H, wl.sigma)
+            assert np.all(M <= T * (1 + REL)), (b, H, np.max(M), T)
+
+
+def _sampled_plane(plane_cpu, x_of, wl, series, n=1500, seed=2):
+    rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
+    Z = O.z_index_max(wl.zmax, wl.dz)
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for row, b in enumerate(series):
+        Ah = _ah((wl.name, b), x_of(b))
+        NR = wl.nsamp - 2 * rlo
+        c = rng.integers(0, NR, n)
+        zi = rng.integers(0, 2 * Z + 1, n)
+        ref = O.plane_cells(Ah, c + 2 * rlo, zi - Z, wl.dz)
+        got = plane_cpu[row][zi, c].astype(np.float64)
+        err = np.abs(got - ref) / np.maximum(ref, 1.0)
+        worst = max(worst, float(err.max()))
+        assert err.max() <= REL, (b, float(err.max()))
+    return worst
+
+
+# ----------------------------------------------------------------------------- FAST batch
+
+@pytest.fixture(scope="module")
+def fast(fdas_gpu):
+    import torch
+    wl = synth.config2()
+    x = synth.generate(wl)
+    xd = torch.from_numpy(x).cuda()
+    plan = fdas_gpu.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm)
+    cands = plan.search(xd, wl.tsamp, sigma=wl.sigma, cap=1 << 20)
+    return wl, x, xd, plan, cands
+
+
+def test_fast_batch_full_candidate_lists_of_two_series(fast):
+    wl, x, _, _, cands = fast
+    carriers = sorted({i.series for i in wl.injections})
+    quiet = next(b for b in range(wl.nseries) if b not in carriers)
+    for b in (carriers[0], quiet):
+        orc = OracleSeries(x[b], wl.tsamp, wl.zmax, wl.dz, wl.numharm, method="fft")
+        mine = cands[cands["series"] == b]
+        assert_candidates_match(mine, {b: orc}, wl.sigma)
+
+
+def test_fast_batch_every_candidate_verified(fast):
+    wl, x, _, _, cands = fast
+    assert len(cands) > 50
+    n = _verify_candidates(cands, lambda b: x[b], wl, max_check=60)
+    assert n >= 50
+
+
+def test_fast_batch_random_columns_are_not_candidates(fast):
+    wl, x, _, _, cands = fast
+    _non_candidates(cands, lambda b: x[b], wl, series=[0, 77, 127])
+
+
+def test_fast_batch_sampled_plane_cells(fast):
+    wl, x, xd, plan, _ = fast
+    P = plan.plane(xd, wl.tsamp)
+    series = [0, 63, wl.injections[0].series]
+    sub = [P[b].cpu().numpy() for b in series]
+    del P
+    _sampled_plane(sub, lambda b: x[b], wl, series)
+
+
+def test_fast_batch_injected_pulsars_found(fast):
+    wl, _, _, _, cands = fast
+    found = 0
+    for inj in wl.injections:
+        mine = cands[cands["series"] == inj.series]
+        ok = (np.abs(mine["r_fund"] - inj.r0) <= 1.0) & (np.abs(mine["z_fund"] - inj.z0) <= 2 * wl.dz + 1)
+        found += bool(ok.any())
+    # the weakest draws (0.05 peak at 10 % duty) sit below sigma 6; most must be found
+    assert found >= len(wl.injections) // 2, found
+
+
+# ----------------------------------------------------------------------------- PMPS long series
+
+@pytest.fixture(scope="module")
+def pmps(fdas_gpu):
+    import torch
+    wl = synth.config3()
+    x = synth.generate(wl)
+    xd = torch.from_numpy(x).cuda()
+    plan = fdas_gpu.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm)
+    cands = plan.search(xd, wl.tsamp, sigma=wl.sigma, cap=1 << 21)
+    return wl, x, xd, plan, cands
+
+
+def test_pmps_every_candidate_verified(pmps):
+    wl, x, _, _, cands = pmps
+    assert len(cands) > 50
+    _verify_candidates(cands, lambda b: x[b], wl, max_check=12)
+
+
+def test_pmps_random_columns_are_not_candidates(pmps):
+    wl, x, _, _, cands = pmps
+    _non_candidates(cands, lambda b: x[b], wl, series=[5], n=12)
+
+
+def test_pmps_rfi_tones_and_pulsars_found(pmps):
+    wl, _, _, _, cands = pmps
+    T = wl.nsamp * wl.tsamp
+    for f in (50.0, 100.0, 150.0):
+        for b in (0, 31):
+            mine = cands[(cands["series"] == b) & (cands["harm"] == 1)]
+            assert np.any(np.abs(mine["f_hz"] - f) * T <= 1.0), (f, b)
+    found = 0
+    for inj in wl.injections:
+        if inj.kind != "pulse":
+            continue
+        mine = cands[cands["series"] == inj.series]
+        ok = (np.abs(mine["r_fund"] - inj.r0) <= 1.0) & (np.abs(mine["z_fund"] - inj.z0) <= 2 * wl.dz + 1)
+        found += bool(ok.any())
+    assert found >= 4, found
+
+
+def test_pmps_sampled_plane_cells(pmps, fdas_gpu):
+    wl, x, xd, _, _ = pmps
+    plan = fdas_gpu.Plan(wl.nsamp, 2, wl.zmax, wl.dz, 1)
+    P = plan.plane(xd[:2].contiguous(), wl.tsamp)
+    sub = [P[0].cpu().numpy(), P[1].cpu().numpy()]
+    del P
+    _sampled_plane(sub, lambda b: x[b], wl, [0, 1], n=400)

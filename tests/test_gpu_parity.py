@@ -231,3 +231,14 @@ def test_invalid_arguments_return_status(fdas_gpu):
     assert e.value.status == F.FDAS_E_UNSUPPORTED
     # the plan still works after rejected calls
     assert plan.search(x, 1e-3, sigma=6.0) is not None
+
+
+def test_harmonic_sum_tile_orders_give_identical_results(fdas_gpu):
+    B, N, ts, zmax, dz, nh = 3, 1 << 14, 1e-3, 40.0, 2.0, 8
+    wl = synth.small_batch(B, N, ts, zmax, dz, nh, config=95, signals=3, amp_range=(0.3, 1.0))
+    x = _cuda(synth.generate(wl))
+    res = [fdas_gpu.Plan(N, B, zmax, dz, nh, harm_order=o).search(x, ts, sigma=3.0, cap=1 << 18)
+           for o in (0, 1, 2, 3)]
+    assert len(res[0]) > 20
+    for r in res[1:]:
+        assert np.array_equal(res[0], r)

@@ -382,3 +382,8 @@ def test_window_maxima_match_full_search():
         i0 = lo - 2 * rlo * H
         assert np.allclose(Mw, M[i0:i0 + 40], rtol=1e-12, atol=0)
         assert np.array_equal(Zw, Zs[i0:i0 + 40])
+
+
+def test_zero_series_normalises_to_zero_power():
+    Ah, norm = O.normalise(O.spectrum(np.zeros(64)))
+    assert norm == 0.0 and not np.any(Ah)
