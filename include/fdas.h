@@ -63,7 +63,11 @@ typedef struct {
     int32_t harm_order;          /* harmonic-sum tile order: 0 automatic, 1 each XCD sweeps its own
                                     series, 2 all XCDs sweep one series at a time, 3 as 2 in two
                                     drift halves (results never depend on it) */
-    int32_t reserved[5];         /* must be zero */
+    int32_t harm_bound;          /* 0: harmonic sums skip drift blocks whose block-maximum bound
+                                    rules out a candidate (exact; default), 1: sum every cell */
+    int32_t harm_block;          /* drift rows per bound block (0 = automatic: 8, 6 or 4 rows
+                                    for numharm <= 8, 16, 32) */
+    int32_t reserved[3];         /* must be zero */
 } fdas_plan_opts;
 
 /* One candidate. r = r_idx/2 and z = z_idx*dz are the Fourier frequency

@@ -36,7 +36,8 @@ class PlanOpts(ctypes.Structure):
                 ("fixed_var", ctypes.c_double), ("max_workspace_bytes", ctypes.c_int64),
                 ("max_candidates", ctypes.c_int64), ("seg_len", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("harm_order", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("harm_bound", ctypes.c_int32), ("harm_block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -94,6 +94,12 @@ struct fdas_plan_s {
     int64_t nblk_cap = 0;
     DevCand *d_rec = nullptr;
     int64_t rec_cap = 0;
+    // drift-row block maxima for the bounded harmonic sums
+    float *d_pyr = nullptr;
+    int64_t pyr_cap = 0;        // floats
+    int32_t *d_rb = nullptr;    // lo[nblk + 1] followed by of_row[NZ]
+    int64_t rb_cap = 0;
+    int rb_NZ = -1, rb_G = -1, rb_bz = -1, rb_nblk = 0;
     // pinned host staging
     int64_t *h_state = nullptr;
     float *h_small = nullptr;   // thresholds / fixed scales
@@ -296,14 +302,51 @@ CorrGeom corr_geom(fdas_plan p, const Geometry &g) {
     return c;
 }
 
+int block_rows(fdas_plan p, int numharm) {
+    if (p->opts.harm_block) return p->opts.harm_block;
+    return numharm <= 8 ? 8 : numharm == 16 ? 6 : 4;
+}
+
+// Row-block tables for the bounded harmonic sums (cached per geometry).
+fdas_status ensure_row_blocks(fdas_plan p, int NZ, int G, int bz, RowBlocks &rb) {
+    if (!(p->d_rb && p->rb_NZ == NZ && p->rb_G == G && p->rb_bz == bz)) {
+        std::vector<int32_t> lo, of_row;
+        row_blocks(NZ, G, bz, lo, of_row);
+        const int64_t n = (int64_t)lo.size() + NZ;
+        if (n > p->rb_cap) {
+            TRY(dalloc(p, &p->d_rb, n, "row-block tables"));
+            p->rb_cap = n;
+        }
+        std::vector<int32_t> both(lo);
+        both.insert(both.end(), of_row.begin(), of_row.end());
+        HIPTRY(p, hipMemcpy(p->d_rb, both.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+        p->rb_NZ = NZ;
+        p->rb_G = G;
+        p->rb_bz = bz;
+        p->rb_nblk = (int)lo.size() - 1;
+    }
+    rb.lo = p->d_rb;
+    rb.of_row = p->d_rb + p->rb_nblk + 1;
+    rb.nblk = p->rb_nblk;
+    return FDAS_OK;
+}
+
 // K5 + K6 + argmax for one chunk of planes.
 fdas_status run_harm_chunk(fdas_plan p, const float *plane, int64_t pitch, int64_t sstride,
-                           const Geometry &g, int numharm, int b0, int nb, hipStream_t st) {
+                           const Geometry &g, int numharm, int b0, int nb, hipStream_t st,
+                           const float *pyr = nullptr, int64_t psstride = 0,
+                           const RowBlocks *rb = nullptr) {
     const int NS = nstages_of(numharm);
     const int64_t mpitch = round_up(g.NR, 16);
     hipEvent_t e = p->begin(st);
-    const int order = p->opts.harm_order ? p->opts.harm_order : 1;
-    HIPTRY(p, launch_harmsum(plane, pitch, sstride, g.NR, g.rlo, g.Z, numharm, nb, p->d_maxv, mpitch, order, st));
+    if (pyr) {
+        HIPTRY(p, launch_harmsum_bounded(plane, pitch, sstride, pyr, psstride, *rb, g.NR, g.rlo, g.Z,
+                                         numharm, nb, p->d_thr, p->d_maxv, mpitch, st));
+    } else {
+        const int order = p->opts.harm_order ? p->opts.harm_order : 1;
+        HIPTRY(p, launch_harmsum(plane, pitch, sstride, g.NR, g.rlo, g.Z, numharm, nb, p->d_maxv, mpitch,
+                                 order, st));
+    }
     p->end(3, e, st);
     const int64_t nelem = (int64_t)nb * NS * mpitch;
     e = p->begin(st);
@@ -431,7 +474,8 @@ void fdas_plan_destroy(fdas_plan p) {
     (void)hipGetDevice(&cur);
     if (p->device >= 0) (void)hipSetDevice(p->device);
     void *dev[] = {p->d_bank, p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_thr,
-                   p->d_state, p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec};
+                   p->d_state, p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec,
+                   p->d_pyr, p->d_rb};
     for (void *q : dev)
         if (q) (void)hipFree(q);
     for (auto &t : p->ev_pending) {
@@ -453,12 +497,13 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     fdas_plan_opts o;
     fdas_plan_opts_default(&o);
     if (opts) o = *opts;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 3; ++i)
         if (o.reserved[i]) return FDAS_E_INVAL;
     if (max_series < 1 || max_series > 65535 || !valid_numharm(numharm) || o.K < 1 || o.K > 1024 ||
         (o.norm != FDAS_NORM_MEDIAN && o.norm != FDAS_NORM_FIXED) ||
         (o.norm == FDAS_NORM_FIXED && !(o.fixed_var > 0)) || o.max_workspace_bytes < 0 ||
-        o.max_candidates < 0 || o.harm_order < 0 || o.harm_order > 3)
+        o.max_candidates < 0 || o.harm_order < 0 || o.harm_order > 3 || o.harm_bound < 0 ||
+        o.harm_bound > 1 || o.harm_block < 0 || o.harm_block > 64)
         return FDAS_E_INVAL;
     Geometry g;
     if (geometry(max_nsamp, 1e-3, zmax, dz, 0.0, g) != FDAS_OK) return FDAS_E_INVAL;
@@ -509,6 +554,12 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     p->chunk_series = (int)chunk;
     p->plane_cap = chunk * per_series;
     if ((s = dalloc(p, &p->d_plane, p->plane_cap, "power plane")) != FDAS_OK) return bail(s);
+    {
+        // block maxima of every chunk series: at most NZ/bz + 8 blocks per series
+        const int bz = block_rows(p, numharm);
+        p->pyr_cap = chunk * (int64_t)(p->bankNZ / bz + 9) * pitch;
+        if ((s = dalloc(p, &p->d_pyr, p->pyr_cap, "block maxima")) != FDAS_OK) return bail(s);
+    }
     const int NS = nstages_of(numharm);
     p->maxv_cap = chunk * NS * round_up(max_nsamp, 16);
     if ((s = dalloc(p, &p->d_maxv, p->maxv_cap, "stage maxima")) != FDAS_OK) return bail(s);
@@ -543,6 +594,13 @@ fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int
     if (sstride > p->plane_cap)
         return p->fail(FDAS_E_INVAL, "one series' plane exceeds the workspace; create the plan with this zmax");
     const int chunk = (int)std::min<int64_t>(p->chunk_series, p->plane_cap / sstride);
+    // bounded harmonic sums need the block maxima of every chunk series
+    // (K4 always writes them, so both harmonic-sum modes read the same plane)
+    RowBlocks rb;
+    TRY(ensure_row_blocks(p, g.NZ, cg.zgroups, block_rows(p, numharm), rb));
+    const int64_t psstride = (int64_t)rb.nblk * pitch;
+    float *pyr = (psstride * chunk <= p->pyr_cap) ? p->d_pyr : nullptr;
+    const float *pyr_k5 = p->opts.harm_bound ? nullptr : pyr;
     for (int attempt = 0; attempt < 2; ++attempt) {
         TRY(run_spectrum(p, series_dev, g, nseries, st));
         TRY(prepare_harm(p, g, numharm, sigma, st));
@@ -550,9 +608,9 @@ fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int
             const int nb = std::min(chunk, nseries - b0);
             hipEvent_t e = p->begin(st);
             HIPTRY(p, launch_corr_power(p->d_spec + (int64_t)b0 * p->spitch, p->spitch, p->d_scale + b0,
-                                        p->d_bank, cg, nb, p->d_plane, pitch, sstride, st));
+                                        p->d_bank, cg, nb, p->d_plane, pitch, sstride, pyr, psstride, rb, st));
             p->end(2, e, st);
-            TRY(run_harm_chunk(p, p->d_plane, pitch, sstride, g, numharm, b0, nb, st));
+            TRY(run_harm_chunk(p, p->d_plane, pitch, sstride, g, numharm, b0, nb, st, pyr_k5, psstride, &rb));
         }
         bool regrow = false;
         fdas_status s = finish(p, g, numharm, dz, out_host, cap, n_total, st, &regrow);
@@ -575,7 +633,7 @@ fdas_status fdas_plane(fdas_plan p, const float *series_dev, int64_t nsamp, int3
     const CorrGeom cg = corr_geom(p, g);
     hipEvent_t e = p->begin(st);
     HIPTRY(p, launch_corr_power(p->d_spec, p->spitch, p->d_scale, p->d_bank, cg, nseries, plane_dev, g.NR,
-                                (int64_t)g.NZ * g.NR, st));
+                                (int64_t)g.NZ * g.NR, nullptr, 0, RowBlocks(), st));
     p->end(2, e, st);
     HIPTRY(p, hipStreamSynchronize(st));
     p->collect();
@@ -596,11 +654,29 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
     const int NS = nstages_of(numharm);
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(p->max_series,
                                                  p->maxv_cap / (NS * round_up(g.NR, 16))));
+    // block maxima of the caller's plane for the bounded sums (row blocks as a
+    // single z group; results do not depend on the partition)
+    RowBlocks rb;
+    int64_t psstride = 0;
+    int pchunk = chunk;
+    if (!p->opts.harm_bound) {
+        TRY(ensure_row_blocks(p, g.NZ, 1, block_rows(p, numharm), rb));
+        psstride = (int64_t)rb.nblk * g.NR;
+        pchunk = (int)std::min<int64_t>(chunk, p->pyr_cap / std::max<int64_t>(1, psstride));
+    }
+    const bool bounded = !p->opts.harm_bound && pchunk >= 1;
+    const int step = bounded ? pchunk : chunk;
     for (int attempt = 0; attempt < 2; ++attempt) {
         TRY(prepare_harm(p, g, numharm, sigma, st));
-        for (int b0 = 0; b0 < nseries; b0 += chunk) {
-            const int nb = std::min(chunk, nseries - b0);
-            TRY(run_harm_chunk(p, plane_dev + (int64_t)b0 * sstride, g.NR, sstride, g, numharm, b0, nb, st));
+        for (int b0 = 0; b0 < nseries; b0 += step) {
+            const int nb = std::min(step, nseries - b0);
+            const float *pl = plane_dev + (int64_t)b0 * sstride;
+            if (bounded) {
+                HIPTRY(p, launch_block_max(pl, g.NR, sstride, g.NR, rb, nb, p->d_pyr, psstride, st));
+                TRY(run_harm_chunk(p, pl, g.NR, sstride, g, numharm, b0, nb, st, p->d_pyr, psstride, &rb));
+            } else {
+                TRY(run_harm_chunk(p, pl, g.NR, sstride, g, numharm, b0, nb, st));
+            }
         }
         bool regrow = false;
         fdas_status s = finish(p, g, numharm, dz, out_host, cap, n_total, st, &regrow);

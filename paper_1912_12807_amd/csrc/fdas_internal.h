@@ -61,9 +61,24 @@ struct CorrGeom {
     int NZ;           // z rows
     int zgroups;      // z rows are split in this many groups (1, 2, 4, 8)
 };
+// Drift-row blocks for the block maxima ("pyramid"): block k covers rows
+// [lo[k], lo[k+1]); blocks never straddle a z group of K4. of_row[r] is the
+// block of row r. Both tables live in device memory.
+struct RowBlocks {
+    const int32_t *lo = nullptr;      // nblk + 1 entries
+    const int32_t *of_row = nullptr;  // NZ entries
+    int nblk = 0;
+};
+// Host construction of the row-block partition for NZ rows, G z groups and
+// blocks of at most bz rows (as even as possible inside each group).
+void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int32_t> &of_row);
+
+// K4. If pyr is not null, K4 also writes pyr[b][k][c] = max over the rows of
+// block k of plane[b][row][c] (pyramid pitch = plane pitch).
 hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *scale,
                              const float2 *bank, const CorrGeom &g, int nseries, float *plane,
-                             int64_t pitch, int64_t series_stride, hipStream_t st);
+                             int64_t pitch, int64_t series_stride, float *pyr,
+                             int64_t pyr_series_stride, const RowBlocks &rb, hipStream_t st);
 
 // K5: harmonic sums and maxima over z for every column and stage.
 // maxv: [nseries][nstages][mpitch] (zero where a stage is not searched).
@@ -73,6 +88,22 @@ hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *sc
 hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
                           int64_t rlo, int Z, int numharm, int nseries, float *maxv,
                           int64_t mpitch, int order, hipStream_t st);
+
+// Block maxima of a caller-supplied plane (what K4 writes alongside its plane).
+hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
+                            const RowBlocks &rb, int nseries, float *pyr, int64_t pyr_series_stride,
+                            hipStream_t st);
+
+// K5 with block bounds: per column and drift block, the stage chain over the
+// block maxima bounds every exact stage sum of the block from above (FP32
+// addition is monotone); only blocks where some searched stage's bound
+// exceeds its threshold are summed exactly. maxv is exact wherever it exceeds
+// the threshold (elsewhere it only stays at or below it), so the candidates
+// equal those of launch_harmsum bit for bit.
+hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
+                                  const float *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
+                                  int64_t NR, int64_t rlo, int Z, int numharm, int nseries,
+                                  const float *thr_dev, float *maxv, int64_t mpitch, hipStream_t st);
 
 // K6: ordered compaction of maxv > thr[stage] into records in (b, s, c) order.
 // The batch may be processed in series chunks: state[0] (device int64) is the

@@ -114,12 +114,15 @@ __device__ __forceinline__ void fft_block(float2 *v, float *lds, int &sel, const
     }
 }
 
-template <int L>
+template <int L, bool PYR>
 __global__ __launch_bounds__(L / 8) void k_corr_power(const float2 *__restrict__ spec, int64_t spitch,
                                                       const float *__restrict__ scale,
                                                       const float2 *__restrict__ bank, CorrGeom g,
                                                       int nseries, float *__restrict__ plane,
-                                                      int64_t pitch, int64_t sstride) {
+                                                      int64_t pitch, int64_t sstride,
+                                                      float *__restrict__ pyr, int64_t psstride,
+                                                      const int32_t *__restrict__ blk_lo,
+                                                      const int32_t *__restrict__ blk_of_row) {
     constexpr int T = Corr<L>::T;
     __shared__ float lds[4 * Corr<L>::LDSZ];
     const int t = threadIdx.x;
@@ -160,6 +163,15 @@ __global__ __launch_bounds__(L / 8) void k_corr_power(const float2 *__restrict__
     for (int q = 0; q < 8; ++q) S[q] = make_float2(S[q].x * sc, S[q].y * sc);
 
     float *out = plane + (int64_t)b * sstride + 2 * (ks - g.rlo);
+    float *pout = PYR ? pyr + (int64_t)b * psstride + 2 * (ks - g.rlo) : nullptr;
+    int blk = 0, blk_end = 0;
+    float m0[8], m1[8];
+    if constexpr (PYR) {
+        blk = blk_of_row[z0];
+        blk_end = blk_lo[blk + 1];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m0[q] = m1[q] = 0.0f;
+    }
     for (int zi = z0; zi < z1; ++zi) {
         float p0[8];
 #pragma unroll
@@ -177,9 +189,26 @@ __global__ __launch_bounds__(L / 8) void k_corr_power(const float2 *__restrict__
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int i = t + q * T;
-                    if (i < g.Lv && ks + i < g.half) {
-                        const float p1 = v[q].x * v[q].x + v[q].y * v[q].y;
+                    const float p1 = v[q].x * v[q].x + v[q].y * v[q].y;
+                    if (i < g.Lv && ks + i < g.half)
                         *reinterpret_cast<float2 *>(row + 2 * i) = make_float2(p0[q], p1);
+                    if constexpr (PYR) {
+                        m0[q] = fmaxf(m0[q], p0[q]);
+                        m1[q] = fmaxf(m1[q], p1);
+                    }
+                }
+                if constexpr (PYR) {
+                    if (zi + 1 == blk_end) {
+                        float *prow = pout + (int64_t)blk * pitch;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int i = t + q * T;
+                            if (i < g.Lv && ks + i < g.half)
+                                *reinterpret_cast<float2 *>(prow + 2 * i) = make_float2(m0[q], m1[q]);
+                            m0[q] = m1[q] = 0.0f;
+                        }
+                        ++blk;
+                        if (zi + 1 < z1) blk_end = blk_lo[blk + 1];
                     }
                 }
             }
@@ -187,35 +216,52 @@ __global__ __launch_bounds__(L / 8) void k_corr_power(const float2 *__restrict__
     }
 }
 
+void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int32_t> &of_row) {
+    lo.clear();
+    of_row.assign(NZ, 0);
+    for (int gi = 0; gi < G; ++gi) {
+        const int z0 = gi * NZ / G, z1 = (gi + 1) * NZ / G;
+        const int n = z1 - z0;
+        if (n <= 0) continue;
+        const int nb = (n + bz - 1) / bz;
+        for (int k = 0; k < nb; ++k) {
+            const int a = z0 + k * n / nb, e = z0 + (k + 1) * n / nb;
+            for (int r = a; r < e; ++r) of_row[r] = (int32_t)lo.size();
+            lo.push_back(a);
+        }
+    }
+    lo.push_back(NZ);
+}
+
+template <int L>
+static void launch_l(const float2 *spec, int64_t spitch, const float *scale, const float2 *bank,
+                     const CorrGeom &g, int nseries, float *plane, int64_t pitch, int64_t sstride,
+                     float *pyr, int64_t psstride, const RowBlocks &rb, int64_t nwg, hipStream_t st) {
+    if (pyr)
+        hipLaunchKernelGGL((k_corr_power<L, true>), dim3((unsigned)nwg), dim3(L / 8), 0, st, spec, spitch,
+                           scale, bank, g, nseries, plane, pitch, sstride, pyr, psstride, rb.lo, rb.of_row);
+    else
+        hipLaunchKernelGGL((k_corr_power<L, false>), dim3((unsigned)nwg), dim3(L / 8), 0, st, spec, spitch,
+                           scale, bank, g, nseries, plane, pitch, sstride, pyr, psstride, rb.lo, rb.of_row);
+}
+
 hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *scale,
                              const float2 *bank, const CorrGeom &g, int nseries, float *plane,
-                             int64_t pitch, int64_t series_stride, hipStream_t st) {
+                             int64_t pitch, int64_t series_stride, float *pyr,
+                             int64_t pyr_series_stride, const RowBlocks &rb, hipStream_t st) {
     if (nseries < 1 || g.nseg < 1 || g.Lv < 1 || (g.zgroups & (g.zgroups - 1)) || g.zgroups > 8 ||
-        g.zgroups < 1 || (pitch & 1))
+        g.zgroups < 1 || (pitch & 1) || (pyr && (!rb.lo || !rb.of_row || rb.nblk < 1)))
         return hipErrorInvalidValue;
     const int64_t units = (int64_t)nseries * g.nseg;
     const int per = 8 / g.zgroups;
     const int64_t nwg = 8 * ((units + per - 1) / per);
     if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
     switch (g.L) {
-    case 512:
-        hipLaunchKernelGGL(k_corr_power<512>, dim3((unsigned)nwg), dim3(64), 0, st, spec, spitch,
-                           scale, bank, g, nseries, plane, pitch, series_stride);
-        break;
-    case 1024:
-        hipLaunchKernelGGL(k_corr_power<1024>, dim3((unsigned)nwg), dim3(128), 0, st, spec, spitch,
-                           scale, bank, g, nseries, plane, pitch, series_stride);
-        break;
-    case 2048:
-        hipLaunchKernelGGL(k_corr_power<2048>, dim3((unsigned)nwg), dim3(256), 0, st, spec, spitch,
-                           scale, bank, g, nseries, plane, pitch, series_stride);
-        break;
-    case 4096:
-        hipLaunchKernelGGL(k_corr_power<4096>, dim3((unsigned)nwg), dim3(512), 0, st, spec, spitch,
-                           scale, bank, g, nseries, plane, pitch, series_stride);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    case 512: launch_l<512>(spec, spitch, scale, bank, g, nseries, plane, pitch, series_stride, pyr, pyr_series_stride, rb, nwg, st); break;
+    case 1024: launch_l<1024>(spec, spitch, scale, bank, g, nseries, plane, pitch, series_stride, pyr, pyr_series_stride, rb, nwg, st); break;
+    case 2048: launch_l<2048>(spec, spitch, scale, bank, g, nseries, plane, pitch, series_stride, pyr, pyr_series_stride, rb, nwg, st); break;
+    case 4096: launch_l<4096>(spec, spitch, scale, bank, g, nseries, plane, pitch, series_stride, pyr, pyr_series_stride, rb, nwg, st); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -149,6 +149,103 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
     for (int s = 0; s < NS; ++s) mo[s * mpitch] = (R >= 2 * rlo * (1 << s)) ? mx[s] : 0.0f;
 }
 
+// Bounded variant: lane = column R, loop over drift blocks. For fraction j the
+// rows a block's sums read, frac_row(zq, j) for zq in the block, lie in at most
+// a few row blocks; the largest block maximum among them bounds every value the
+// fraction contributes. The stage chain of these bounds (same order as the
+// exact chain) bounds every exact stage sum of the block, so a block whose
+// bounds stay at or below all searched stages' thresholds cannot hold a
+// candidate and is skipped. Block bounds stay cached per fraction while its
+// (wave-uniform) row-block range is unchanged. A block that some lane of the
+// wave cannot rule out is summed exactly by the whole wave. With 32
+// fractions the per-fraction cache would need 64 wave-uniform indices, more
+// than the scalar register file holds, so that instance re-reads each
+// block's bounds instead.
+template <int NH, bool CACHE>
+__global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ plane, int64_t pitch,
+                                                    int64_t sstride, const float *__restrict__ pyr,
+                                                    int64_t psstride, const int32_t *__restrict__ blk_lo,
+                                                    const int32_t *__restrict__ blk_of_row, int nblk,
+                                                    int64_t NR, int64_t rlo, int Z,
+                                                    const float *__restrict__ thr,
+                                                    float *__restrict__ maxv, int64_t mpitch,
+                                                    int64_t tiles_per_series, int64_t total_tiles) {
+    constexpr int NS = Stages<NH>::NS;
+    const int64_t g = blockIdx.x;
+    if (g >= total_tiles) return;
+    const int b = (int)(g / tiles_per_series);
+    const int64_t c = (g - (int64_t)b * tiles_per_series) * 256 + threadIdx.x;
+    if (c >= mpitch) return;
+    float *mo = maxv + (int64_t)b * NS * mpitch + c;
+    if (c >= NR) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) mo[s * mpitch] = 0.0f;
+        return;
+    }
+    const int64_t R = c + 2 * rlo;
+    int64_t col[NH];
+    const uint32_t need = column_offsets<NH>(R, rlo, col);
+    const float *pb = plane + (int64_t)b * sstride + (int64_t)Z * pitch;   // row Zq = 0
+    const float *yb = pyr + (int64_t)b * psstride;
+    float th[NS];
+    bool valid[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        th[s] = thr[s];
+        valid[s] = R >= 2 * rlo * (1 << s);
+    }
+    float mx[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) mx[s] = 0.0f;
+
+    int ba[NH], bb[NH];
+    float bv[NH];
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+        ba[j] = -1;
+        bb[j] = -1;
+        bv[j] = 0.0f;
+    }
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int zqa = blk_lo[kb] - Z;
+        const int zqb = blk_lo[kb + 1] - 1 - Z;
+        float B[NH];
+#pragma unroll
+        for (int j = 1; j <= NH; ++j) {
+            const int a = blk_of_row[frac_row<NH>(zqa, j) + Z];
+            const int e = blk_of_row[frac_row<NH>(zqb, j) + Z];
+            if (!CACHE || a != ba[j - 1] || e != bb[j - 1]) {
+                if (CACHE) {
+                    ba[j - 1] = a;
+                    bb[j - 1] = e;
+                }
+                float v = 0.0f;
+                if ((need >> (j - 1)) & 1u) {
+                    for (int k = a; k <= e; ++k) v = fmaxf(v, yb[(int64_t)k * pitch + col[j - 1]]);
+                }
+                bv[j - 1] = v;
+            }
+            B[j - 1] = bv[j - 1];
+        }
+        float U[NS];
+        stage_chain<NH>(B, U);
+        bool hot = false;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) hot |= valid[s] && (U[s] > th[s]);
+        if (__any(hot)) {
+            for (int zq = zqa; zq <= zqb; ++zq) {
+                float P[NH], Ss[NS];
+                gather<NH>(pb - (int64_t)Z * pitch, pitch, Z, zq, col, need, P);
+                stage_chain<NH>(P, Ss);
+#pragma unroll
+                for (int s = 0; s < NS; ++s) mx[s] = fmaxf(mx[s], Ss[s]);
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) mo[s * mpitch] = valid[s] ? mx[s] : 0.0f;
+}
+
 template <int NH>
 __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ plane, int64_t pitch,
                                                 int64_t sstride, int64_t rlo, int Z, int b0,
@@ -184,6 +281,33 @@ __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ plane,
         }
         if (lane == 0) rec[i].zq = best;
     }
+}
+
+// Block maxima of a caller-supplied plane: pyr[b][k][c] = max over the rows
+// of block k of plane[b][row][c] (K4 writes the same quantity while it builds
+// the plane).
+__global__ __launch_bounds__(256) void k_block_max(const float *__restrict__ plane, int64_t pitch,
+                                                   int64_t sstride, int64_t NR,
+                                                   const int32_t *__restrict__ blk_lo, int nblk,
+                                                   float *__restrict__ pyr, int64_t psstride) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y, b = blockIdx.z;
+    if (c >= NR || k >= nblk) return;
+    const float *src = plane + (int64_t)b * sstride + c;
+    float m = 0.0f;
+    for (int r = blk_lo[k]; r < blk_lo[k + 1]; ++r) m = fmaxf(m, src[(int64_t)r * pitch]);
+    pyr[(int64_t)b * psstride + (int64_t)k * pitch + c] = m;
+}
+
+hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
+                            const RowBlocks &rb, int nseries, float *pyr, int64_t pyr_series_stride,
+                            hipStream_t st) {
+    if (nseries < 1 || nseries > 65535 || rb.nblk < 1 || rb.nblk > 65535 || !rb.lo)
+        return hipErrorInvalidValue;
+    dim3 grid((unsigned)((NR + 255) / 256), (unsigned)rb.nblk, (unsigned)nseries);
+    hipLaunchKernelGGL(k_block_max, grid, dim3(256), 0, st, plane, pitch, series_stride, NR, rb.lo,
+                       rb.nblk, pyr, pyr_series_stride);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ compaction
@@ -338,6 +462,37 @@ hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stri
     case 32: launch_harm_nh<32>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <int NH>
+static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, const float *pyr,
+                            int64_t psstride, const RowBlocks &rb, int64_t NR, int64_t rlo, int Z,
+                            int nseries, const float *thr, float *maxv, int64_t mpitch, hipStream_t st) {
+    const int64_t tps = (mpitch + 255) / 256;
+    const int64_t total = tps * nseries;
+    hipLaunchKernelGGL((k_harm_bound<NH, (NH <= 16)>), dim3((unsigned)total), dim3(256), 0, st, plane, pitch, sstride,
+                       pyr, psstride, rb.lo, rb.of_row, rb.nblk, NR, rlo, Z, thr, maxv, mpitch, tps, total);
+}
+
+hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
+                                  const float *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
+                                  int64_t NR, int64_t rlo, int Z, int numharm, int nseries,
+                                  const float *thr_dev, float *maxv, int64_t mpitch, hipStream_t st) {
+    if (nseries < 1 || mpitch < NR || (mpitch & 15) || (mpitch + 255) / 256 * nseries > 0x7ffffff0LL ||
+        !pyr || !rb.lo || !rb.of_row || rb.nblk < 1)
+        return hipErrorInvalidValue;
+#define FDAS_BOUND(NHV) launch_bound_nh<NHV>(plane, pitch, series_stride, pyr, pyr_series_stride, rb, NR, rlo, Z, nseries, thr_dev, maxv, mpitch, st)
+    switch (numharm) {
+    case 1: FDAS_BOUND(1); break;
+    case 2: FDAS_BOUND(2); break;
+    case 4: FDAS_BOUND(4); break;
+    case 8: FDAS_BOUND(8); break;
+    case 16: FDAS_BOUND(16); break;
+    case 32: FDAS_BOUND(32); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef FDAS_BOUND
     return hipGetLastError();
 }
 

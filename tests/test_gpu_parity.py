@@ -95,8 +95,9 @@ def test_plane_fixed_norm_noise_free_peak(fdas_gpu):
 
 # ----------------------------------------------------------------------------- harmonic sums
 
+@pytest.mark.parametrize("bound", [0, 1], ids=["bounded", "exhaustive"])
 @pytest.mark.parametrize("numharm", [1, 2, 4, 8, 16, 32])
-def test_harmsum_bit_exact_on_integer_planes(fdas_gpu, numharm):
+def test_harmsum_bit_exact_on_integer_planes(fdas_gpu, numharm, bound):
     import torch
     B, N, ts, zmax, dz = 3, 1 << 12, 1e-2, 6.0, 2.0
     rlo = O.rlo_bins(N, ts)
@@ -108,7 +109,7 @@ def test_harmsum_bit_exact_on_integer_planes(fdas_gpu, numharm):
         for _ in range(20):
             planes[b, rng.integers(0, 2 * Z + 1), rng.integers(0, N - 2 * rlo)] = rng.integers(100, 4000)
     sigma = 6.0
-    plan = fdas_gpu.Plan(N, B, zmax, dz, numharm)
+    plan = fdas_gpu.Plan(N, B, zmax, dz, numharm, harm_bound=bound)
     g = plan.harmsum(torch.from_numpy(planes).cuda(), N, ts, sigma=sigma, cap=1 << 18)
     got = sorted((int(c["series"]), int(c["harm"]), int(c["r_idx"]), int(c["z_idx"]), float(c["power"]))
                  for c in g)
@@ -242,3 +243,48 @@ def test_harmonic_sum_tile_orders_give_identical_results(fdas_gpu):
     assert len(res[0]) > 20
     for r in res[1:]:
         assert np.array_equal(res[0], r)
+
+
+BOUND_CASES = [
+    # (B, N, tsamp, zmax, dz, numharm, sigma, block)
+    (3, 1 << 14, 1e-3, 40.0, 2.0, 8, 6.0, 0),
+    (3, 1 << 14, 1e-3, 40.0, 2.0, 8, 3.0, 0),     # low threshold: most blocks summed exactly
+    (2, 1 << 14, 1e-3, 200.0, 2.0, 16, 5.0, 0),
+    (2, 1 << 13, 2e-3, 10.0, 1.0, 32, 4.0, 0),
+    (2, 1 << 13, 1e-3, 0.0, 2.0, 4, 4.0, 0),      # one drift row
+    (2, 1 << 14, 1e-3, 60.0, 2.0, 8, 5.0, 1),     # one row per block
+    (2, 1 << 14, 1e-3, 60.0, 2.0, 8, 5.0, 61),    # one block per z group
+]
+
+
+@pytest.mark.parametrize("case", BOUND_CASES, ids=lambda c: f"N{c[1]}-z{c[3]}-h{c[5]}-s{c[6]}-bz{c[7]}")
+def test_bounded_harmonic_sums_equal_exhaustive(fdas_gpu, case):
+    B, N, ts, zmax, dz, nh, sigma, bz = case
+    wl = synth.small_batch(B, N, ts, zmax, dz, nh, sigma=sigma, config=96, signals=B,
+                           amp_range=(0.3, 1.0))
+    x = _cuda(synth.generate(wl))
+    ref = fdas_gpu.Plan(N, B, zmax, dz, nh, harm_bound=1).search(x, ts, sigma=sigma, cap=1 << 18)
+    got = fdas_gpu.Plan(N, B, zmax, dz, nh, harm_block=bz).search(x, ts, sigma=sigma, cap=1 << 18)
+    assert len(ref) > 5
+    if not np.array_equal(ref, got):
+        kr = {tuple(int(v) for v in (c["series"], c["harm"], c["r_idx"], c["z_idx"])): float(c["power"]) for c in ref}
+        kg = {tuple(int(v) for v in (c["series"], c["harm"], c["r_idx"], c["z_idx"])): float(c["power"]) for c in got}
+        only_r = sorted(set(kr) - set(kg))[:10]
+        only_g = sorted(set(kg) - set(kr))[:10]
+        diff = [(k, kr[k], kg[k]) for k in sorted(set(kr) & set(kg)) if kr[k] != kg[k]][:10]
+        raise AssertionError(f"exhaustive only {only_r}; bounded only {only_g}; power differs {diff}")
+
+
+@pytest.mark.parametrize("numharm,bz", [(8, 0), (16, 0), (32, 0), (32, 3), (4, 1)])
+def test_bounded_harmsum_bit_exact_on_the_same_float_plane(fdas_gpu, numharm, bz):
+    """Bounded and exhaustive harmonic sums of one caller plane give identical records."""
+    import torch
+    B, N, ts, zmax, dz = 2, 1 << 14, 1e-3, 30.0, 2.0
+    wl = synth.small_batch(B, N, ts, zmax, dz, numharm, config=97, signals=B, amp_range=(0.3, 1.0))
+    x = _cuda(synth.generate(wl))
+    P = fdas_gpu.Plan(N, B, zmax, dz, numharm).plane(x, ts)
+    sig = 3.5
+    ref = fdas_gpu.Plan(N, B, zmax, dz, numharm, harm_bound=1).harmsum(P, N, ts, sigma=sig, cap=1 << 18)
+    got = fdas_gpu.Plan(N, B, zmax, dz, numharm, harm_block=bz).harmsum(P, N, ts, sigma=sig, cap=1 << 18)
+    assert len(ref) > 20
+    assert np.array_equal(ref, got)
