@@ -65,9 +65,10 @@ typedef struct {
                                     drift halves (results never depend on it) */
     int32_t harm_bound;          /* 0: harmonic sums skip drift blocks whose block-maximum bound
                                     rules out a candidate (exact; default), 1: sum every cell */
-    int32_t harm_block;          /* drift rows per bound block (0 = automatic: 8, 6 or 4 rows
-                                    for numharm <= 8, 16, 32) */
-    int32_t reserved[3];         /* must be zero */
+    int32_t harm_block;          /* drift rows per bound block (0 = automatic) */
+    int32_t harm_pair;           /* 0: block maxima per bin, covering both half-bin columns
+                                    (default); 1: per column (tighter bound, twice the memory) */
+    int32_t reserved[2];         /* must be zero */
 } fdas_plan_opts;
 
 /* One candidate. r = r_idx/2 and z = z_idx*dz are the Fourier frequency

@@ -37,7 +37,7 @@ class PlanOpts(ctypes.Structure):
                 ("max_candidates", ctypes.c_int64), ("seg_len", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("harm_order", ctypes.c_int32),
                 ("harm_bound", ctypes.c_int32), ("harm_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("harm_pair", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -45,27 +45,31 @@ def _compile(src: str, flags, obj: str):
     return r.stderr
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, out: str = None, obj_dir: str = None, defines=()) -> str:
+    """Compile and link; out/obj_dir/defines let tuning builds go elsewhere."""
+    lib = out or LIB
+    obj = obj_dir or OBJ
+    os.makedirs(obj, exist_ok=True)
+    extra = [f"-D{d}" for d in defines]
     hip, cpp = sources()
     jobs = []
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
         for f in hip:
-            jobs.append(ex.submit(_compile, f, HIP_FLAGS, os.path.join(OBJ, f + ".o")))
+            jobs.append(ex.submit(_compile, f, HIP_FLAGS + extra, os.path.join(obj, f + ".o")))
         for f in cpp:
-            jobs.append(ex.submit(_compile, f, ["-x", "c++"] + HOST_FLAGS, os.path.join(OBJ, f + ".o")))
+            jobs.append(ex.submit(_compile, f, ["-x", "c++"] + HOST_FLAGS + extra, os.path.join(obj, f + ".o")))
         for j in jobs:
             err = j.result()
             if verbose and err:
                 print(err, file=sys.stderr)
-    objs = [os.path.join(OBJ, f + ".o") for f in hip + cpp]
-    tmp = LIB + ".tmp"
+    objs = [os.path.join(obj, f + ".o") for f in hip + cpp]
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

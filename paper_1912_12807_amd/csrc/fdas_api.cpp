@@ -99,7 +99,7 @@ struct fdas_plan_s {
     int64_t pyr_cap = 0;        // floats
     int32_t *d_rb = nullptr;    // lo[nblk + 1] followed by of_row[NZ]
     int64_t rb_cap = 0;
-    int rb_NZ = -1, rb_G = -1, rb_bz = -1, rb_nblk = 0;
+    int rb_NZ = -1, rb_G = -1, rb_bz = -1, rb_nh = -1, rb_nblk = 0;
     // pinned host staging
     int64_t *h_state = nullptr;
     float *h_small = nullptr;   // thresholds / fixed scales
@@ -304,30 +304,37 @@ CorrGeom corr_geom(fdas_plan p, const Geometry &g) {
 
 int block_rows(fdas_plan p, int numharm) {
     if (p->opts.harm_block) return p->opts.harm_block;
-    return numharm <= 8 ? 8 : numharm == 16 ? 6 : 4;
+    return numharm <= 8 ? 10 : numharm == 16 ? 8 : 6;
 }
 
-// Row-block tables for the bounded harmonic sums (cached per geometry).
-fdas_status ensure_row_blocks(fdas_plan p, int NZ, int G, int bz, RowBlocks &rb) {
-    if (!(p->d_rb && p->rb_NZ == NZ && p->rb_G == G && p->rb_bz == bz)) {
-        std::vector<int32_t> lo, of_row;
+// Row-block tables for the bounded harmonic sums (cached per geometry):
+// lo[nblk + 1], of_row[NZ], frange[nblk][numharm] in one device buffer.
+fdas_status ensure_row_blocks(fdas_plan p, int NZ, int G, int bz, int numharm, RowBlocks &rb) {
+    if (!(p->d_rb && p->rb_NZ == NZ && p->rb_G == G && p->rb_bz == bz && p->rb_nh == numharm)) {
+        std::vector<int32_t> lo, of_row, fr;
         row_blocks(NZ, G, bz, lo, of_row);
-        const int64_t n = (int64_t)lo.size() + NZ;
+        fraction_ranges(NZ, numharm, lo, of_row, fr);
+        std::vector<int32_t> all(lo);
+        all.insert(all.end(), of_row.begin(), of_row.end());
+        all.insert(all.end(), fr.begin(), fr.end());
+        const int64_t n = (int64_t)all.size();
         if (n > p->rb_cap) {
             TRY(dalloc(p, &p->d_rb, n, "row-block tables"));
             p->rb_cap = n;
         }
-        std::vector<int32_t> both(lo);
-        both.insert(both.end(), of_row.begin(), of_row.end());
-        HIPTRY(p, hipMemcpy(p->d_rb, both.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPTRY(p, hipMemcpy(p->d_rb, all.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
         p->rb_NZ = NZ;
         p->rb_G = G;
         p->rb_bz = bz;
+        p->rb_nh = numharm;
         p->rb_nblk = (int)lo.size() - 1;
     }
     rb.lo = p->d_rb;
     rb.of_row = p->d_rb + p->rb_nblk + 1;
+    rb.frange = rb.of_row + NZ;
     rb.nblk = p->rb_nblk;
+    rb.frange_nh = numharm;
+    rb.pair = p->opts.harm_pair == 0;   // default: maxima per bin (pair); 1 selects per column
     return FDAS_OK;
 }
 
@@ -497,13 +504,14 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     fdas_plan_opts o;
     fdas_plan_opts_default(&o);
     if (opts) o = *opts;
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (o.reserved[i]) return FDAS_E_INVAL;
     if (max_series < 1 || max_series > 65535 || !valid_numharm(numharm) || o.K < 1 || o.K > 1024 ||
         (o.norm != FDAS_NORM_MEDIAN && o.norm != FDAS_NORM_FIXED) ||
         (o.norm == FDAS_NORM_FIXED && !(o.fixed_var > 0)) || o.max_workspace_bytes < 0 ||
         o.max_candidates < 0 || o.harm_order < 0 || o.harm_order > 3 || o.harm_bound < 0 ||
-        o.harm_bound > 1 || o.harm_block < 0 || o.harm_block > 64)
+        o.harm_bound > 1 || o.harm_block < 0 || o.harm_block > 64 || o.harm_pair < 0 ||
+        o.harm_pair > 1)
         return FDAS_E_INVAL;
     Geometry g;
     if (geometry(max_nsamp, 1e-3, zmax, dz, 0.0, g) != FDAS_OK) return FDAS_E_INVAL;
@@ -557,7 +565,7 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     {
         // block maxima of every chunk series: at most NZ/bz + 8 blocks per series
         const int bz = block_rows(p, numharm);
-        p->pyr_cap = chunk * (int64_t)(p->bankNZ / bz + 9) * pitch;
+        p->pyr_cap = chunk * (int64_t)(p->bankNZ / bz + 9) * (o.harm_pair == 0 ? pitch / 2 : pitch);
         if ((s = dalloc(p, &p->d_pyr, p->pyr_cap, "block maxima")) != FDAS_OK) return bail(s);
     }
     const int NS = nstages_of(numharm);
@@ -597,10 +605,11 @@ fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int
     // bounded harmonic sums need the block maxima of every chunk series
     // (K4 always writes them, so both harmonic-sum modes read the same plane)
     RowBlocks rb;
-    TRY(ensure_row_blocks(p, g.NZ, cg.zgroups, block_rows(p, numharm), rb));
-    const int64_t psstride = (int64_t)rb.nblk * pitch;
+    TRY(ensure_row_blocks(p, g.NZ, cg.zgroups, block_rows(p, numharm), numharm, rb));
+    const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? pitch / 2 : pitch);
     float *pyr = (psstride * chunk <= p->pyr_cap) ? p->d_pyr : nullptr;
-    const float *pyr_k5 = p->opts.harm_bound ? nullptr : pyr;
+    const float *pyr_k5 = (p->opts.harm_bound || bounded_lds_bytes(rb.nblk, numharm) > kBoundLdsMax)
+                              ? nullptr : pyr;
     for (int attempt = 0; attempt < 2; ++attempt) {
         TRY(run_spectrum(p, series_dev, g, nseries, st));
         TRY(prepare_harm(p, g, numharm, sigma, st));
@@ -660,11 +669,12 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
     int64_t psstride = 0;
     int pchunk = chunk;
     if (!p->opts.harm_bound) {
-        TRY(ensure_row_blocks(p, g.NZ, 1, block_rows(p, numharm), rb));
-        psstride = (int64_t)rb.nblk * g.NR;
+        TRY(ensure_row_blocks(p, g.NZ, 1, block_rows(p, numharm), numharm, rb));
+        psstride = (int64_t)rb.nblk * (rb.pair ? g.NR / 2 : g.NR);
         pchunk = (int)std::min<int64_t>(chunk, p->pyr_cap / std::max<int64_t>(1, psstride));
     }
-    const bool bounded = !p->opts.harm_bound && pchunk >= 1;
+    const bool bounded = !p->opts.harm_bound && pchunk >= 1 &&
+                         bounded_lds_bytes(rb.nblk, numharm) <= kBoundLdsMax;
     const int step = bounded ? pchunk : chunk;
     for (int attempt = 0; attempt < 2; ++attempt) {
         TRY(prepare_harm(p, g, numharm, sigma, st));

@@ -67,14 +67,26 @@ struct CorrGeom {
 struct RowBlocks {
     const int32_t *lo = nullptr;      // nblk + 1 entries
     const int32_t *of_row = nullptr;  // NZ entries
+    const int32_t *frange = nullptr;  // [nblk][frange_nh]: row blocks a..e that fraction j of
+                                      // block k reads, packed a | (e - a) << 24
     int nblk = 0;
+    int frange_nh = 0;
+    bool pair = false;                // maxima per bin (both parities) instead of per column
 };
 // Host construction of the row-block partition for NZ rows, G z groups and
 // blocks of at most bz rows (as even as possible inside each group).
 void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int32_t> &of_row);
+// Host table of the row blocks each harmonic fraction of each block reads.
+void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
+                     const std::vector<int32_t> &of_row, std::vector<int32_t> &frange);
+constexpr size_t kBoundLdsMax = 48 * 1024;
+inline size_t bounded_lds_bytes(int nblk, int numharm) {
+    return (size_t)(nblk + 1 + (size_t)nblk * numharm) * sizeof(int32_t);
+}
 
-// K4. If pyr is not null, K4 also writes pyr[b][k][c] = max over the rows of
-// block k of plane[b][row][c] (pyramid pitch = plane pitch).
+// K4. If pyr is not null, K4 also writes the block maxima: pyr[b][k][c] = max
+// over the rows of block k of plane[b][row][c] (pitch = plane pitch), or with
+// rb.pair the maximum over columns 2i and 2i+1 at pyr[b][k][i] (pitch / 2).
 hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *scale,
                              const float2 *bank, const CorrGeom &g, int nseries, float *plane,
                              int64_t pitch, int64_t series_stride, float *pyr,

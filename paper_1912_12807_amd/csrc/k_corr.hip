@@ -13,10 +13,10 @@
 //
 // FFT layout: L points over T = L/8 threads, thread t holding points t + q T
 // (q = 0..7) in natural order before every pass. Stockham radix-8 passes with
-// Ns = 1, 8, 64, then a radix-(L/512) pass, exchange through padded LDS (one
-// pad word per 8, separate re/im arrays, ping-pong buffers, one barrier per
-// exchange); after the last pass each thread again holds t + q T, so plane
-// rows are written as coalesced float2 (p = 0, p = 1) pairs.
+// Ns = 1, 8, 64, then a radix-(L/512) pass, exchange through LDS (separate
+// re/im arrays, a bank-conflict-free layout per exchange, ping-pong buffers,
+// one barrier per exchange); after the last pass each thread again holds
+// t + q T, so plane rows are written with coalesced stores.
 //
 // Work is split so that each XCD (workgroup id mod 8) only touches one group
 // of z rows: its slice of the template bank stays in that XCD's L2.
@@ -29,15 +29,35 @@ template <int L>
 struct Corr {
     static constexpr int T = L / 8;          // threads per workgroup
     static constexpr int R4 = L / 512;       // radix of the fourth pass (1: none)
-    static constexpr int LDSZ = L + L / 8;   // padded floats per array
-    static constexpr int RS = 9 * T / 8;     // padded stride between a thread's points
-    static constexpr int NTW4 = R4 > 1 ? (8 / R4) * (R4 - 1) : 1;
+    static constexpr int LDSZ = L + L / 8;   // floats per array (largest padded layout)
+    // read strides between a thread's points t + q T in the three exchange layouts
+    static constexpr int RS1 = T + T / 64;   // layout 1: word p at p + p/64
+    static constexpr int RS2 = T + T / 8;    // layout 2: word p at p + 8 (p/64)
+    static constexpr int RS3 = T;            // layout 3: word p at p
 };
 
 template <int L>
 struct Twiddles {
-    float2 p2[7], p3[7], p4[Corr<L>::NTW4];
+    // pass-4 twiddles are kept for the first butterfly only: the butterfly u
+    // twiddle exp(2 pi i (t + u T) r / L) is that of u = 0 rotated by
+    // exp(i pi u r / 4), since T / L = 1/8
+    float2 p2[7], p3[7], p4[Corr<L>::R4 > 1 ? Corr<L>::R4 - 1 : 1];
 };
+
+// a * exp(i pi K / 4) for a compile-time K
+template <int K>
+__device__ __forceinline__ float2 rot8(float2 a) {
+    constexpr float h = 0.70710678118654752440f;
+    constexpr int k = K & 7;
+    if constexpr (k == 0) return a;
+    else if constexpr (k == 1) return make_float2(h * (a.x - a.y), h * (a.x + a.y));
+    else if constexpr (k == 2) return make_float2(-a.y, a.x);
+    else if constexpr (k == 3) return make_float2(h * (-a.x - a.y), h * (a.x - a.y));
+    else if constexpr (k == 4) return make_float2(-a.x, -a.y);
+    else if constexpr (k == 5) return make_float2(h * (a.y - a.x), h * (-a.x - a.y));
+    else if constexpr (k == 6) return make_float2(a.y, -a.x);
+    else return make_float2(h * (a.x + a.y), h * (a.y - a.x));
+}
 
 template <int L>
 __device__ __forceinline__ void make_twiddles(Twiddles<L> &tw, int t) {
@@ -49,19 +69,48 @@ __device__ __forceinline__ void make_twiddles(Twiddles<L> &tw, int t) {
     }
     constexpr int R4 = Corr<L>::R4;
     if constexpr (R4 > 1) {
-        constexpr int B = 8 / R4;
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const int k = t + u * Corr<L>::T;                // < 512
-#pragma unroll
-            for (int r = 1; r < R4; ++r)
-                tw.p4[u * (R4 - 1) + r - 1] = expipi((float)(2 * k * r) / (float)L);
-        }
+        for (int r = 1; r < R4; ++r) tw.p4[r - 1] = expipi((float)(2 * t * r) / (float)L);
     }
 }
 
-// write v[r] at wbase + r*WS of buffer sel, barrier, read the thread's points back
-template <int L, int WS>
+// twiddle of butterfly U, input R of pass 4, for direction DIR applied to a
+template <int L, int DIR, int U, int R>
+__device__ __forceinline__ float2 pass4_twiddle(float2 a, const Twiddles<L> &tw) {
+    const float2 w = rot8<U * R>(tw.p4[R - 1]);
+    return ctw<DIR>(a, w);
+}
+
+template <int L, int DIR, int U, int R4, int B>
+__device__ __forceinline__ void pass4_butterfly(float2 *v, const Twiddles<L> &tw) {
+    float2 w[R4];
+#pragma unroll
+    for (int r = 0; r < R4; ++r) w[r] = v[U + r * B];
+    if constexpr (R4 >= 2) w[1] = pass4_twiddle<L, DIR, U, 1>(w[1], tw);
+    if constexpr (R4 >= 4) {
+        w[2] = pass4_twiddle<L, DIR, U, 2>(w[2], tw);
+        w[3] = pass4_twiddle<L, DIR, U, 3>(w[3], tw);
+    }
+    if constexpr (R4 >= 8) {
+        w[4] = pass4_twiddle<L, DIR, U, 4>(w[4], tw);
+        w[5] = pass4_twiddle<L, DIR, U, 5>(w[5], tw);
+        w[6] = pass4_twiddle<L, DIR, U, 6>(w[6], tw);
+        w[7] = pass4_twiddle<L, DIR, U, 7>(w[7], tw);
+    }
+    dft_r<R4, DIR>(w);
+#pragma unroll
+    for (int r = 0; r < R4; ++r) v[U + r * B] = w[r];
+}
+
+// write v[r] at wbase + r*WS of buffer sel, barrier, read the thread's points
+// back from rbase + q*RS.
+//
+// Each exchange has its own layout, chosen so that a wave's 64 lanes hit 64
+// distinct LDS banks both when writing the pass outputs (position 8t + r after
+// pass 1, 64(t/8) + t%8 + 8r after pass 2, 512(t/64) + t%64 + 64r after pass
+// 3) and when reading t + qT back: word p is stored at p + p/64 (exchange 1),
+// p + 8(p/64) (exchange 2) and p (exchange 3).
+template <int L, int WS, int RS>
 __device__ __forceinline__ void exchange(float2 *v, float *lds, int &sel, int wbase, int rbase) {
     float *re = lds + sel * 2 * Corr<L>::LDSZ;
     float *im = re + Corr<L>::LDSZ;
@@ -72,12 +121,12 @@ __device__ __forceinline__ void exchange(float2 *v, float *lds, int &sel, int wb
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = make_float2(re[rbase + q * Corr<L>::RS], im[rbase + q * Corr<L>::RS]);
+    for (int q = 0; q < 8; ++q) v[q] = make_float2(re[rbase + q * RS], im[rbase + q * RS]);
     sel ^= 1;
 }
 
 struct LdsAddr {
-    int w1, w2, w3, rd;
+    int w1, w2, w3, r1, r2, r3;
 };
 
 template <int L, int DIR>
@@ -85,37 +134,39 @@ __device__ __forceinline__ void fft_block(float2 *v, float *lds, int &sel, const
                                           const LdsAddr &a) {
     // pass 1: radix 8, Ns = 1
     dft8<DIR>(v);
-    exchange<L, 1>(v, lds, sel, a.w1, a.rd);
+    exchange<L, 1, Corr<L>::RS1>(v, lds, sel, a.w1, a.r1);
     // pass 2: radix 8, Ns = 8
 #pragma unroll
     for (int r = 1; r < 8; ++r) v[r] = ctw<DIR>(v[r], tw.p2[r - 1]);
     dft8<DIR>(v);
-    exchange<L, 9>(v, lds, sel, a.w2, a.rd);
+    exchange<L, 8, Corr<L>::RS2>(v, lds, sel, a.w2, a.r2);
     // pass 3: radix 8, Ns = 64
 #pragma unroll
     for (int r = 1; r < 8; ++r) v[r] = ctw<DIR>(v[r], tw.p3[r - 1]);
     dft8<DIR>(v);
     constexpr int R4 = Corr<L>::R4;
     if constexpr (R4 > 1) {
-        exchange<L, 72>(v, lds, sel, a.w3, a.rd);
+        exchange<L, 64, Corr<L>::RS3>(v, lds, sel, a.w3, a.r3);
         // pass 4: radix R4, Ns = 512, butterflies u use points v[u + r * (8 / R4)]
         constexpr int B = 8 / R4;
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-            float2 w[R4 > 1 ? R4 : 1];
-#pragma unroll
-            for (int r = 0; r < R4; ++r) w[r] = v[u + r * B];
-#pragma unroll
-            for (int r = 1; r < R4; ++r) w[r] = ctw<DIR>(w[r], tw.p4[u * (R4 - 1) + r - 1]);
-            dft_r<R4, DIR>(w);
-#pragma unroll
-            for (int r = 0; r < R4; ++r) v[u + r * B] = w[r];
+        pass4_butterfly<L, DIR, 0, R4, B>(v, tw);
+        if constexpr (B >= 2) pass4_butterfly<L, DIR, 1, R4, B>(v, tw);
+        if constexpr (B >= 4) {
+            pass4_butterfly<L, DIR, 2, R4, B>(v, tw);
+            pass4_butterfly<L, DIR, 3, R4, B>(v, tw);
         }
     }
 }
 
-template <int L, bool PYR>
-__global__ __launch_bounds__(L / 8) void k_corr_power(const float2 *__restrict__ spec, int64_t spitch,
+// Minimum waves per SIMD requested from the register allocator (build-time tuning).
+#ifndef FDAS_K4_MIN_WAVES
+#define FDAS_K4_MIN_WAVES 1
+#endif
+
+// PYR: 0 no block maxima, 1 one maximum per column (half bin), 2 one per bin
+// (both parities).
+template <int L, int PYR>
+__global__ __launch_bounds__(L / 8, FDAS_K4_MIN_WAVES) void k_corr_power(const float2 *__restrict__ spec, int64_t spitch,
                                                       const float *__restrict__ scale,
                                                       const float2 *__restrict__ bank, CorrGeom g,
                                                       int nseries, float *__restrict__ plane,
@@ -143,10 +194,12 @@ __global__ __launch_bounds__(L / 8) void k_corr_power(const float2 *__restrict__
     Twiddles<L> tw;
     make_twiddles<L>(tw, t);
     LdsAddr a;
-    a.w1 = 9 * t;
-    a.w2 = (t >> 3) * 72 + (t & 7);
-    a.w3 = (t >> 6) * 576 + (t & 63) + ((t & 63) >> 3);
-    a.rd = t + (t >> 3);
+    a.w1 = 8 * t + (t >> 3);                 // pass-1 output 8t + r in layout 1
+    a.w2 = 72 * (t >> 3) + (t & 7);          // pass-2 output 64(t/8) + t%8 + 8r in layout 2
+    a.w3 = 512 * (t >> 6) + (t & 63);        // pass-3 output 512(t/64) + t%64 + 64r in layout 3
+    a.r1 = t + (t >> 6);
+    a.r2 = t + 8 * (t >> 6);
+    a.r3 = t;
     int sel = 0;
 
     // segment s[n] = A[ks - mseg + n], zero outside bins 1..half-1
@@ -163,17 +216,19 @@ __global__ __launch_bounds__(L / 8) void k_corr_power(const float2 *__restrict__
     for (int q = 0; q < 8; ++q) S[q] = make_float2(S[q].x * sc, S[q].y * sc);
 
     float *out = plane + (int64_t)b * sstride + 2 * (ks - g.rlo);
-    float *pout = PYR ? pyr + (int64_t)b * psstride + 2 * (ks - g.rlo) : nullptr;
+    // block-maxima row: pitch floats per block (PYR 1), pitch/2 (PYR 2)
+    const int64_t ppitch = PYR == 2 ? pitch / 2 : pitch;
+    float *pout = PYR ? pyr + (int64_t)b * psstride + (PYR == 2 ? 1 : 2) * (ks - g.rlo) : nullptr;
     int blk = 0, blk_end = 0;
     float m0[8], m1[8];
-    if constexpr (PYR) {
+    if constexpr (PYR != 0) {
         blk = blk_of_row[z0];
         blk_end = blk_lo[blk + 1];
 #pragma unroll
         for (int q = 0; q < 8; ++q) m0[q] = m1[q] = 0.0f;
     }
     for (int zi = z0; zi < z1; ++zi) {
-        float p0[8];
+        float *row = out + (int64_t)zi * pitch;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             const float2 *Tz = bank + (int64_t)(2 * zi + p) * L;
@@ -181,36 +236,31 @@ __global__ __launch_bounds__(L / 8) void k_corr_power(const float2 *__restrict__
 #pragma unroll
             for (int q = 0; q < 8; ++q) v[q] = cmul(S[q], Tz[t + q * T]);
             fft_block<L, 1>(v, lds, sel, tw, a);
-            if (p == 0) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) p0[q] = v[q].x * v[q].x + v[q].y * v[q].y;
-            } else {
-                float *row = out + (int64_t)zi * pitch;
+            for (int q = 0; q < 8; ++q) {
+                const int i = t + q * T;
+                const float pw = v[q].x * v[q].x + v[q].y * v[q].y;
+                if (i < g.Lv && ks + i < g.half) row[2 * i + p] = pw;
+                if constexpr (PYR != 0) {
+                    if (PYR == 2 || p == 0) m0[q] = fmaxf(m0[q], pw);
+                    else m1[q] = fmaxf(m1[q], pw);
+                }
+            }
+        }
+        if constexpr (PYR != 0) {
+            if (zi + 1 == blk_end) {
+                float *prow = pout + (int64_t)blk * ppitch;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int i = t + q * T;
-                    const float p1 = v[q].x * v[q].x + v[q].y * v[q].y;
-                    if (i < g.Lv && ks + i < g.half)
-                        *reinterpret_cast<float2 *>(row + 2 * i) = make_float2(p0[q], p1);
-                    if constexpr (PYR) {
-                        m0[q] = fmaxf(m0[q], p0[q]);
-                        m1[q] = fmaxf(m1[q], p1);
+                    if (i < g.Lv && ks + i < g.half) {
+                        if constexpr (PYR == 2) prow[i] = m0[q];
+                        else *reinterpret_cast<float2 *>(prow + 2 * i) = make_float2(m0[q], m1[q]);
                     }
+                    m0[q] = m1[q] = 0.0f;
                 }
-                if constexpr (PYR) {
-                    if (zi + 1 == blk_end) {
-                        float *prow = pout + (int64_t)blk * pitch;
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            const int i = t + q * T;
-                            if (i < g.Lv && ks + i < g.half)
-                                *reinterpret_cast<float2 *>(prow + 2 * i) = make_float2(m0[q], m1[q]);
-                            m0[q] = m1[q] = 0.0f;
-                        }
-                        ++blk;
-                        if (zi + 1 < z1) blk_end = blk_lo[blk + 1];
-                    }
-                }
+                ++blk;
+                if (zi + 1 < z1) blk_end = blk_lo[blk + 1];
             }
         }
     }
@@ -233,16 +283,37 @@ void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int
     lo.push_back(NZ);
 }
 
+void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
+                     const std::vector<int32_t> &of_row, std::vector<int32_t> &frange) {
+    const int Z = (NZ - 1) / 2;
+    const int nblk = (int)lo.size() - 1;
+    auto frow = [&](int zq, int j) {
+        const int az = zq < 0 ? -zq : zq;
+        const int r = (2 * az * j + numharm) / (2 * numharm);
+        return zq < 0 ? -r : r;
+    };
+    frange.assign((size_t)nblk * numharm, 0);
+    for (int k = 0; k < nblk; ++k) {
+        const int zqa = lo[k] - Z, zqb = lo[k + 1] - 1 - Z;
+        for (int j = 1; j <= numharm; ++j) {
+            const int a = of_row[frow(zqa, j) + Z], e = of_row[frow(zqb, j) + Z];
+            frange[(size_t)k * numharm + j - 1] = a | ((e - a) << 24);
+        }
+    }
+}
+
 template <int L>
 static void launch_l(const float2 *spec, int64_t spitch, const float *scale, const float2 *bank,
                      const CorrGeom &g, int nseries, float *plane, int64_t pitch, int64_t sstride,
                      float *pyr, int64_t psstride, const RowBlocks &rb, int64_t nwg, hipStream_t st) {
-    if (pyr)
-        hipLaunchKernelGGL((k_corr_power<L, true>), dim3((unsigned)nwg), dim3(L / 8), 0, st, spec, spitch,
-                           scale, bank, g, nseries, plane, pitch, sstride, pyr, psstride, rb.lo, rb.of_row);
-    else
-        hipLaunchKernelGGL((k_corr_power<L, false>), dim3((unsigned)nwg), dim3(L / 8), 0, st, spec, spitch,
-                           scale, bank, g, nseries, plane, pitch, sstride, pyr, psstride, rb.lo, rb.of_row);
+    const int mode = pyr ? (rb.pair ? 2 : 1) : 0;
+#define FDAS_K4(M)                                                                                  \
+    hipLaunchKernelGGL((k_corr_power<L, M>), dim3((unsigned)nwg), dim3(L / 8), 0, st, spec, spitch, \
+                       scale, bank, g, nseries, plane, pitch, sstride, pyr, psstride, rb.lo, rb.of_row)
+    if (mode == 0) FDAS_K4(0);
+    else if (mode == 1) FDAS_K4(1);
+    else FDAS_K4(2);
+#undef FDAS_K4
 }
 
 hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *scale,

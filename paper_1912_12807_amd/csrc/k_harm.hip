@@ -150,43 +150,78 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
 }
 
 // Bounded variant: lane = column R, loop over drift blocks. For fraction j the
-// rows a block's sums read, frac_row(zq, j) for zq in the block, lie in at most
-// a few row blocks; the largest block maximum among them bounds every value the
-// fraction contributes. The stage chain of these bounds (same order as the
-// exact chain) bounds every exact stage sum of the block, so a block whose
-// bounds stay at or below all searched stages' thresholds cannot hold a
-// candidate and is skipped. Block bounds stay cached per fraction while its
-// (wave-uniform) row-block range is unchanged. A block that some lane of the
-// wave cannot rule out is summed exactly by the whole wave. With 32
-// fractions the per-fraction cache would need 64 wave-uniform indices, more
-// than the scalar register file holds, so that instance re-reads each
-// block's bounds instead.
-template <int NH, bool CACHE>
+// rows a block's sums read, frac_row(zq, j) for zq in the block, lie in row
+// blocks a..e (a host table, staged in LDS; packed as a | (e - a) << 24); the
+// largest block maximum among them (maxima cover both half-bin columns of a
+// bin) bounds every value the fraction contributes. The stage chain of these bounds (same order as the exact
+// chain) bounds every exact stage sum of the block, so a block whose bounds
+// stay at or below all searched stages' thresholds cannot hold a candidate and
+// is skipped. The next block's bounds are loaded while the current one is
+// tested. A block that some lane of the wave cannot rule out is summed exactly
+// by the whole wave.
+template <int NH>
+struct BoundCfg {
+    // series per lane: the wave-uniform block bookkeeping is shared by SB series
+    static constexpr int SB = NH <= 8 ? 4 : NH == 16 ? 2 : 1;
+};
+
+template <int NH>
 __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ plane, int64_t pitch,
                                                     int64_t sstride, const float *__restrict__ pyr,
                                                     int64_t psstride, const int32_t *__restrict__ blk_lo,
-                                                    const int32_t *__restrict__ blk_of_row, int nblk,
+                                                    const int32_t *__restrict__ frange, int nblk,
                                                     int64_t NR, int64_t rlo, int Z,
                                                     const float *__restrict__ thr,
                                                     float *__restrict__ maxv, int64_t mpitch,
-                                                    int64_t tiles_per_series, int64_t total_tiles) {
+                                                    int64_t tiles_per_series, int64_t total_tiles,
+                                                    int pair, int nseries) {
     constexpr int NS = Stages<NH>::NS;
-    const int64_t g = blockIdx.x;
+    constexpr int SB = BoundCfg<NH>::SB;
+    extern __shared__ int32_t sm[];            // blk_lo[nblk + 1], then frange[nblk][NH]
+    for (int i = threadIdx.x; i < nblk + 1; i += 256) sm[i] = blk_lo[i];
+    for (int i = threadIdx.x; i < nblk * NH; i += 256) sm[nblk + 1 + i] = frange[i];
+    __syncthreads();
+    const int32_t *slo = sm;
+    const int32_t *sfr = sm + nblk + 1;
+
+    // each XCD (workgroup id mod 8) takes a contiguous run of (series group,
+    // column tile) items: neighbouring tiles read overlapping fraction strips
+    // through its L2
+    const int64_t w = blockIdx.x;
+    const int64_t per_xcd = (total_tiles + 7) / 8;
+    const int64_t g = (w & 7) * per_xcd + (w >> 3);
     if (g >= total_tiles) return;
-    const int b = (int)(g / tiles_per_series);
-    const int64_t c = (g - (int64_t)b * tiles_per_series) * 256 + threadIdx.x;
+    const int grp = (int)(g / tiles_per_series);
+    const int b0 = grp * SB;
+    const int64_t c = (g - (int64_t)grp * tiles_per_series) * 256 + threadIdx.x;
     if (c >= mpitch) return;
-    float *mo = maxv + (int64_t)b * NS * mpitch + c;
     if (c >= NR) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) mo[s * mpitch] = 0.0f;
+        for (int m = 0; m < SB; ++m) {
+            if (b0 + m >= nseries) break;
+            float *mo = maxv + (int64_t)(b0 + m) * NS * mpitch + c;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) mo[s * mpitch] = 0.0f;
+        }
         return;
     }
     const int64_t R = c + 2 * rlo;
     int64_t col[NH];
     const uint32_t need = column_offsets<NH>(R, rlo, col);
-    const float *pb = plane + (int64_t)b * sstride + (int64_t)Z * pitch;   // row Zq = 0
-    const float *yb = pyr + (int64_t)b * psstride;
+    // block-maxima column of each fraction (clamped to a valid column when unused)
+    int32_t colp[NH];
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+        const int64_t cc = col[j] < 0 ? 0 : col[j];
+        colp[j] = (int32_t)(pair ? cc >> 1 : cc);
+    }
+    const float *yb[SB];
+#pragma unroll
+    for (int m = 0; m < SB; ++m) {
+        const int bm = b0 + m < nseries ? b0 + m : nseries - 1;   // spare lanes re-read the last series
+        yb[m] = pyr + (int64_t)bm * psstride;
+    }
+    const int ppitch = (int)(pair ? pitch / 2 : pitch);   // block maxima per bin or per column
     float th[NS];
     bool valid[NS];
 #pragma unroll
@@ -194,56 +229,77 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         th[s] = thr[s];
         valid[s] = R >= 2 * rlo * (1 << s);
     }
-    float mx[NS];
+    float mx[SB][NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) mx[s] = 0.0f;
+    for (int m = 0; m < SB; ++m)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) mx[m][s] = 0.0f;
 
-    int ba[NH], bb[NH];
-    float bv[NH];
+    for (int k0 = 0; k0 < nblk; k0 += 64) {
+        // pass 1: per series, a wave-uniform mask of the blocks some lane cannot rule out
+        uint64_t hotmask[SB];
 #pragma unroll
-    for (int j = 0; j < NH; ++j) {
-        ba[j] = -1;
-        bb[j] = -1;
-        bv[j] = 0.0f;
-    }
-    for (int kb = 0; kb < nblk; ++kb) {
-        const int zqa = blk_lo[kb] - Z;
-        const int zqb = blk_lo[kb + 1] - 1 - Z;
-        float B[NH];
+        for (int m = 0; m < SB; ++m) hotmask[m] = 0;
+        const int kend = nblk - k0 < 64 ? nblk - k0 : 64;
+        for (int kk = 0; kk < kend; ++kk) {
+            const int32_t *fr = sfr + (k0 + kk) * NH;
+            float B[SB][NH];
+            // first row block of every range: unconditional, independent loads
 #pragma unroll
-        for (int j = 1; j <= NH; ++j) {
-            const int a = blk_of_row[frac_row<NH>(zqa, j) + Z];
-            const int e = blk_of_row[frac_row<NH>(zqb, j) + Z];
-            if (!CACHE || a != ba[j - 1] || e != bb[j - 1]) {
-                if (CACHE) {
-                    ba[j - 1] = a;
-                    bb[j - 1] = e;
-                }
-                float v = 0.0f;
-                if ((need >> (j - 1)) & 1u) {
-                    for (int k = a; k <= e; ++k) v = fmaxf(v, yb[(int64_t)k * pitch + col[j - 1]]);
-                }
-                bv[j - 1] = v;
+            for (int j = 0; j < NH; ++j) {
+                const int32_t off = (fr[j] & 0xffffff) * ppitch + colp[j];
+#pragma unroll
+                for (int m = 0; m < SB; ++m) B[m][j] = yb[m][off];
             }
-            B[j - 1] = bv[j - 1];
-        }
-        float U[NS];
-        stage_chain<NH>(B, U);
-        bool hot = false;
+            // further row blocks of ranges that span several (wave-uniform branch)
 #pragma unroll
-        for (int s = 0; s < NS; ++s) hot |= valid[s] && (U[s] > th[s]);
-        if (__any(hot)) {
-            for (int zq = zqa; zq <= zqb; ++zq) {
-                float P[NH], Ss[NS];
-                gather<NH>(pb - (int64_t)Z * pitch, pitch, Z, zq, col, need, P);
-                stage_chain<NH>(P, Ss);
+            for (int j = 0; j < NH; ++j) {
+                const int a = fr[j] & 0xffffff, n = fr[j] >> 24;
+                for (int k = 1; k <= n; ++k) {
+                    const int32_t off = (a + k) * ppitch + colp[j];
 #pragma unroll
-                for (int s = 0; s < NS; ++s) mx[s] = fmaxf(mx[s], Ss[s]);
+                    for (int m = 0; m < SB; ++m) B[m][j] = fmaxf(B[m][j], yb[m][off]);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < SB; ++m) {
+#pragma unroll
+                for (int j = 0; j < NH; ++j) B[m][j] = ((need >> j) & 1u) ? B[m][j] : 0.0f;
+                float U[NS];
+                stage_chain<NH>(B[m], U);
+                bool hot = false;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) hot |= valid[s] && (U[s] > th[s]);
+                if (__any(hot)) hotmask[m] |= 1ull << kk;
             }
         }
+        // pass 2: exact sums of the hot blocks
+#pragma unroll
+        for (int m = 0; m < SB; ++m) {
+            if (b0 + m >= nseries) break;
+            const float *pb = plane + (int64_t)(b0 + m) * sstride;
+            uint64_t hm = hotmask[m];
+            while (hm) {
+                const int kb = k0 + __builtin_ctzll(hm);
+                hm &= hm - 1;
+                const int zqa = slo[kb] - Z, zqb = slo[kb + 1] - 1 - Z;
+                for (int zq = zqa; zq <= zqb; ++zq) {
+                    float P[NH], Ss[NS];
+                    gather<NH>(pb, pitch, Z, zq, col, need, P);
+                    stage_chain<NH>(P, Ss);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) mx[m][s] = fmaxf(mx[m][s], Ss[s]);
+                }
+            }
+        }
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) mo[s * mpitch] = valid[s] ? mx[s] : 0.0f;
+    for (int m = 0; m < SB; ++m) {
+        if (b0 + m >= nseries) break;
+        float *mo = maxv + (int64_t)(b0 + m) * NS * mpitch + c;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) mo[s * mpitch] = valid[s] ? mx[m][s] : 0.0f;
+    }
 }
 
 template <int NH>
@@ -283,30 +339,36 @@ __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ plane,
     }
 }
 
-// Block maxima of a caller-supplied plane: pyr[b][k][c] = max over the rows
-// of block k of plane[b][row][c] (K4 writes the same quantity while it builds
-// the plane).
+// Block maxima of a caller-supplied plane (what K4 writes while it builds the
+// plane): per column, pyr[b][k][c] = max over the rows of block k of
+// plane[b][row][c]; with pair, pyr[b][k][i] covers columns 2i and 2i+1.
 __global__ __launch_bounds__(256) void k_block_max(const float *__restrict__ plane, int64_t pitch,
                                                    int64_t sstride, int64_t NR,
                                                    const int32_t *__restrict__ blk_lo, int nblk,
-                                                   float *__restrict__ pyr, int64_t psstride) {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+                                                   float *__restrict__ pyr, int64_t psstride, int pair) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int k = blockIdx.y, b = blockIdx.z;
-    if (c >= NR || k >= nblk) return;
-    const float *src = plane + (int64_t)b * sstride + c;
-    float m = 0.0f;
-    for (int r = blk_lo[k]; r < blk_lo[k + 1]; ++r) m = fmaxf(m, src[(int64_t)r * pitch]);
-    pyr[(int64_t)b * psstride + (int64_t)k * pitch + c] = m;
+    const int64_t ncol = pair ? NR / 2 : NR;
+    if (i >= ncol || k >= nblk) return;
+    const float *src = plane + (int64_t)b * sstride + (pair ? 2 * i : i);
+    float mx = 0.0f;
+    for (int r = blk_lo[k]; r < blk_lo[k + 1]; ++r) {
+        const float *q = src + (int64_t)r * pitch;
+        mx = fmaxf(mx, pair ? fmaxf(q[0], q[1]) : q[0]);
+    }
+    pyr[(int64_t)b * psstride + (int64_t)k * (pair ? pitch / 2 : pitch) + i] = mx;
 }
 
 hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
                             const RowBlocks &rb, int nseries, float *pyr, int64_t pyr_series_stride,
                             hipStream_t st) {
-    if (nseries < 1 || nseries > 65535 || rb.nblk < 1 || rb.nblk > 65535 || !rb.lo)
+    if (nseries < 1 || nseries > 65535 || rb.nblk < 1 || rb.nblk > 65535 || !rb.lo || (pitch & 1) ||
+        (NR & 1))
         return hipErrorInvalidValue;
-    dim3 grid((unsigned)((NR + 255) / 256), (unsigned)rb.nblk, (unsigned)nseries);
+    const int64_t ncol = rb.pair ? NR / 2 : NR;
+    dim3 grid((unsigned)((ncol + 255) / 256), (unsigned)rb.nblk, (unsigned)nseries);
     hipLaunchKernelGGL(k_block_max, grid, dim3(256), 0, st, plane, pitch, series_stride, NR, rb.lo,
-                       rb.nblk, pyr, pyr_series_stride);
+                       rb.nblk, pyr, pyr_series_stride, rb.pair ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -470,17 +532,23 @@ static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, 
                             int64_t psstride, const RowBlocks &rb, int64_t NR, int64_t rlo, int Z,
                             int nseries, const float *thr, float *maxv, int64_t mpitch, hipStream_t st) {
     const int64_t tps = (mpitch + 255) / 256;
-    const int64_t total = tps * nseries;
-    hipLaunchKernelGGL((k_harm_bound<NH, (NH <= 16)>), dim3((unsigned)total), dim3(256), 0, st, plane, pitch, sstride,
-                       pyr, psstride, rb.lo, rb.of_row, rb.nblk, NR, rlo, Z, thr, maxv, mpitch, tps, total);
+    const int64_t groups = (nseries + BoundCfg<NH>::SB - 1) / BoundCfg<NH>::SB;
+    const int64_t total = tps * groups;
+    const int64_t nwg = 8 * ((total + 7) / 8);
+    const size_t lds = (size_t)(rb.nblk + 1 + rb.nblk * NH) * sizeof(int32_t);
+    hipLaunchKernelGGL(k_harm_bound<NH>, dim3((unsigned)nwg), dim3(256), lds, st, plane, pitch, sstride,
+                       pyr, psstride, rb.lo, rb.frange, rb.nblk, NR, rlo, Z, thr, maxv, mpitch, tps, total,
+                       rb.pair ? 1 : 0, nseries);
 }
 
 hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
                                   const float *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
                                   int64_t NR, int64_t rlo, int Z, int numharm, int nseries,
                                   const float *thr_dev, float *maxv, int64_t mpitch, hipStream_t st) {
+    // block-maxima offsets within one series are 32-bit in the kernel
     if (nseries < 1 || mpitch < NR || (mpitch & 15) || (mpitch + 255) / 256 * nseries > 0x7ffffff0LL ||
-        !pyr || !rb.lo || !rb.of_row || rb.nblk < 1)
+        !pyr || !rb.lo || !rb.frange || rb.nblk < 1 || rb.frange_nh != numharm ||
+        bounded_lds_bytes(rb.nblk, numharm) > kBoundLdsMax || pyr_series_stride > 0x7fffffffLL)
         return hipErrorInvalidValue;
 #define FDAS_BOUND(NHV) launch_bound_nh<NHV>(plane, pitch, series_stride, pyr, pyr_series_stride, rb, NR, rlo, Z, nseries, thr_dev, maxv, mpitch, st)
     switch (numharm) {
