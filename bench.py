@@ -33,6 +33,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK = 157.3       # TFLOP/s, 256 CUs x 2.4 GHz x 256 FP32 flop/clk
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {"plane": "k_corr.hip", "harmsum": "k_harm.hip"}
+DOMINANT = {"plane": "k_corr_power", "harmsum": "k_harm_bound"}
 
 
 def _workload(config: int):
@@ -99,6 +100,83 @@ def cpu_baseline(config: int, wl, nr: int, nz: int, max_cores: int = 16):
             "cpu": model}
 
 
+# ----------------------------------------------------------------------------- profile summaries
+
+def _kernel_key(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def stats_summary(stats_csv: str, title: str, command: str) -> str:
+    """Markdown table of a rocprofv3 --kernel-trace --stats CSV."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    out = [f"# {title}", "", "Command (repository root on the GPU box as $REPO):", "", "```", command, "```", "",
+           "| kernel | calls | avg us | share % |", "|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{_kernel_key(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, workload: str, command: str):
+    """HBM bytes per launch of the search kernels from FETCH_SIZE/WRITE_SIZE (KiB per dispatch).
+
+    Each counter is scaled by what it reads for the 1 GiB device copy that
+    --copy-calibration runs in the same process (known 1 GiB read, 1 GiB written).
+    """
+    import csv
+    import collections
+
+    def load(path):
+        per = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            per[_kernel_key(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return per
+
+    fe, wr = load(fetch_csv), load(write_csv)
+    gib_kib = float(1 << 20)
+    cw = [v for v in wr.get("__amd_rocclr_copyBuffer", []) if abs(v - gib_kib) < 0.01 * gib_kib]
+    cf = sorted(fe.get("__amd_rocclr_copyBuffer", []))[-len(cw):] if cw else []
+    if not cw or not cf:
+        raise RuntimeError("calibration copy not found in the counter output")
+    f_scale = gib_kib / (sum(cf) / len(cf))
+    w_scale = gib_kib / (sum(cw) / len(cw))
+    res = {}
+    lines = [f"# HBM traffic per launch: {workload}", "", "Commands (repository root on the GPU box as $REPO):", "",
+             "```", command, "```", "",
+             f"Calibration: a 1 GiB device copy reads FETCH_SIZE {sum(cf) / len(cf):.0f} KiB and WRITE_SIZE "
+             f"{sum(cw) / len(cw):.0f} KiB, so FETCH is scaled by {f_scale:.3f} and WRITE by {w_scale:.3f}.", "",
+             "| kernel | launches | fetched GB | written GB | total GB |", "|---|---|---|---|---|"]
+    for k in sorted(set(fe) & set(wr)):
+        if not k.startswith("fdas::"):
+            continue
+        f = sum(fe[k]) / len(fe[k]) * 1024 * f_scale
+        w = sum(wr[k]) / len(wr[k]) * 1024 * w_scale
+        res[k] = {"fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w, "launches": len(fe[k])}
+        lines.append(f"| `{k}` | {len(fe[k])} | {f / 1e9:.3f} | {w / 1e9:.3f} | {(f + w) / 1e9:.3f} |")
+    return res, "\n".join(lines) + "\n", f_scale, w_scale
+
+
+def write_traffic(res, workload, f_scale, w_scale):
+    """profiles/traffic.json entries for the dominant-kernel candidates, keyed by source hash."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        data = {}
+    names = {"plane": "fdas::k_corr_power", "harmsum": "fdas::k_harm_bound"}
+    for phase, prefix in names.items():
+        hits = [v for k, v in res.items() if k.startswith(prefix)]
+        if hits:
+            data[f"{workload}:{phase}"] = {"bytes_per_launch": hits[0]["bytes_per_launch"],
+                                           "fetch_bytes": hits[0]["fetch_bytes"],
+                                           "write_bytes": hits[0]["write_bytes"],
+                                           "fetch_scale": f_scale, "write_scale": w_scale,
+                                           "kernel_hash": kernel_hash(phase)}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +187,25 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
+    ap.add_argument("--stats-summary", nargs=3, metavar=("STATS_CSV", "OUT_MD", "COMMAND"),
+                    help="write a markdown summary of a rocprofv3 kernel-stats CSV and exit")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND"),
+                    help="summarise FETCH_SIZE/WRITE_SIZE runs into OUT_MD and profiles/traffic.json")
     args = ap.parse_args()
+    if args.stats_summary:
+        csv_path, out_md, cmd = args.stats_summary
+        wl = _workload(args.config)
+        with open(out_md, "w") as fh:
+            fh.write(stats_summary(csv_path, f"Kernel time summary: {wl.name}", cmd))
+        return
+    if args.pmc_summary:
+        fcsv, wcsv, out_md, cmd = args.pmc_summary
+        wl = _workload(args.config)
+        res, md, fs, ws = pmc_summary(fcsv, wcsv, wl.name, cmd)
+        with open(out_md, "w") as fh:
+            fh.write(md)
+        write_traffic(res, wl.name, fs, ws)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build measures the search on one GPU only; series shard across "
@@ -133,7 +229,6 @@ def main():
     rlo, nr, nz = fdas.geometry(wl.nsamp, wl.tsamp, wl.zmax, wl.dz)
     cells = wl.nseries * nr * nz
     plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1)
-    info = plan.info()
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -159,11 +254,13 @@ def main():
     value = cells * args.steps / wall
 
     # dominant kernel and its roofline
+    info = plan.info()
     phases = {k: v[0] / args.steps for k, v in prof.items()}
     dom = max(("plane", "harmsum"), key=lambda k: prof[k][0])
     launches = max(1, prof[dom][1])
     t_launch = prof[dom][0] / 1e3 / launches           # s
-    cells_launch = cells / (launches / args.steps)
+    per_launch = launches / args.steps                 # launches of the kernel per search
+    cells_launch = cells / per_launch
     L, mseg = info["seg_len"], info["mseg"]
     Lv = L - 2 * mseg
     NS = int(math.log2(wl.numharm)) + 1
@@ -174,18 +271,25 @@ def main():
         G = 1
         while G < 8 and nz >= 2 * G * 12:
             G *= 2
-        flops = (wl.nseries / (launches / args.steps)) * nseg * (
+        flops = (wl.nseries / per_launch) * nseg * (
             2 * nz * (5 * L * math.log2(L) + 9 * L) + G * (5 * L * math.log2(L) + 2 * L))
         achieved = flops / t_launch / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VECTOR_PEAK, "kernel": "k_corr_power",
+                "frac": achieved / FP32_VECTOR_PEAK, "kernel": DOMINANT[dom],
                 "per_unit": f"{flops / cells_launch:.1f} FLOP/cell"}
     else:
-        byts = cells_launch * 4.0 + (cells_launch / nz) * NS * 4.0
+        ser = wl.nseries / per_launch
+        mp_ = (nr + 15) // 16 * 16
+        if info["harm_blocks"]:
+            # bounded sums read the drift-block maxima once and write the stage maxima
+            ncols = nr // 2 if info["harm_pair"] else nr
+            byts = ser * (info["harm_blocks"] * ncols + NS * mp_) * 4.0
+        else:
+            byts = cells_launch * 4.0 + ser * NS * mp_ * 4.0
         achieved = byts / t_launch / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "kernel": "k_harmsum",
-                "per_unit": f"{4.0 + NS * 4.0 / nz:.3f} B/cell"}
+                "frac": achieved / HBM_PEAK_GBS, "kernel": DOMINANT[dom] if info["harm_blocks"] else "k_harmsum",
+                "per_unit": f"{byts / cells_launch:.3f} B/cell"}
     roof["traffic"] = measured_traffic(dom, wl.name)
     roof["launch_ms"] = t_launch * 1e3
 

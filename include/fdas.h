@@ -161,13 +161,17 @@ fdas_status fdas_template_taps(double z, int32_t parity, int32_t K, double *re, 
 
 /* What a plan chose for its current template bank: overlap-save segment
  * length and shared half-width (each segment yields seg_len - 2 mseg valid
- * bins), z rows, series per plane chunk and the plane workspace in bytes. */
+ * bins), z rows, series per plane chunk, the plane workspace in bytes, and,
+ * for the last search, the number of drift blocks of the bounded harmonic
+ * sums (0 if they were not used) and whether their maxima cover bin pairs. */
 typedef struct {
     int32_t seg_len;
     int32_t mseg;
     int32_t nz;
     int32_t chunk_series;
     int64_t workspace_bytes;
+    int32_t harm_blocks;
+    int32_t harm_pair;
 } fdas_plan_info;
 fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out);
 

@@ -42,7 +42,8 @@ class PlanOpts(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("seg_len", ctypes.c_int32), ("mseg", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("chunk_series", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
+                ("chunk_series", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
+                ("harm_blocks", ctypes.c_int32), ("harm_pair", ctypes.c_int32)]
 
 
 CAND_DTYPE = np.dtype([("series", "<i4"), ("harm", "<i4"), ("r_idx", "<i8"), ("z_idx", "<i4"),

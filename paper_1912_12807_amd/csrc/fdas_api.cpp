@@ -100,6 +100,7 @@ struct fdas_plan_s {
     int32_t *d_rb = nullptr;    // lo[nblk + 1] followed by of_row[NZ]
     int64_t rb_cap = 0;
     int rb_NZ = -1, rb_G = -1, rb_bz = -1, rb_nh = -1, rb_nblk = 0;
+    int last_harm_blocks = 0, last_harm_pair = 0;   // what the last search's K5 used
     // pinned host staging
     int64_t *h_state = nullptr;
     float *h_small = nullptr;   // thresholds / fixed scales
@@ -610,6 +611,8 @@ fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int
     float *pyr = (psstride * chunk <= p->pyr_cap) ? p->d_pyr : nullptr;
     const float *pyr_k5 = (p->opts.harm_bound || bounded_lds_bytes(rb.nblk, numharm) > kBoundLdsMax)
                               ? nullptr : pyr;
+    p->last_harm_blocks = pyr_k5 ? rb.nblk : 0;
+    p->last_harm_pair = rb.pair ? 1 : 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         TRY(run_spectrum(p, series_dev, g, nseries, st));
         TRY(prepare_harm(p, g, numharm, sigma, st));
@@ -733,6 +736,8 @@ fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out) {
     out->nz = p->bankNZ;
     out->chunk_series = p->chunk_series;
     out->workspace_bytes = p->plane_cap * (int64_t)sizeof(float);
+    out->harm_blocks = p->last_harm_blocks;
+    out->harm_pair = p->last_harm_pair;
     return FDAS_OK;
 }
 
