@@ -38,7 +38,7 @@ DOMINANT = {"plane": "k_corr_power", "harmsum": "k_harm_bound"}
 
 def _workload(config: int):
     import synth
-    return {1: synth.config1, 2: synth.config2, 3: synth.config3}[config]()
+    return {1: synth.config1, 2: synth.config2, 3: synth.config3, 4: synth.config4}[config]()
 
 
 def kernel_hash(phase: str) -> str:
@@ -73,6 +73,47 @@ def _oracle_series(args):
     return time.perf_counter() - t0
 
 
+def _oracle_ragged_series(args):
+    config, b = args
+    import oracle as O
+    import synth
+    wl = _workload(config)
+    x = synth.generate_series(wl, b)
+    t0 = time.perf_counter()
+    O.search_series(x, wl.tsamp[b], wl.zmax[b], wl.dz, wl.numharm, wl.sigma, series=b)
+    return time.perf_counter() - t0
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def cpu_baseline_ragged(config: int, wl, cells_of, max_cores: int = 16, max_nsamp: int = 1 << 17):
+    """The FP64 oracle on the first series of at most max_nsamp samples, one process each."""
+    import multiprocessing as mp
+    cores = max(1, min(max_cores, len(os.sched_getaffinity(0))))
+    pick = [b for b in range(wl.nseries) if wl.nsamp[b] <= max_nsamp][:cores]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(pick)) as pool:
+        per = pool.map(_oracle_ragged_series, [(config, b) for b in pick])
+    wall = time.perf_counter() - t0
+    cells = sum(cells_of[b] for b in pick)
+    return {"value": cells / wall, "unit": "cells/s", "cores": len(pick), "kind": "oracle",
+            "sample": f"the first {len(pick)} series of at most {max_nsamp} samples of the uneven batch "
+                      f"(zmax {sorted({wl.zmax[b] for b in pick})}), one oracle process per series, "
+                      f"full plane + harmonic sums + candidates in FP64 ({wall:.1f} s wall, "
+                      f"{sum(per) / len(pick):.1f} s per series)",
+            "cpu": _cpu_model()}
+
+
 def cpu_baseline(config: int, wl, nr: int, nz: int, max_cores: int = 16):
     """The FP64 oracle, one process per series (the paper's process-level strategy)."""
     import multiprocessing as mp
@@ -84,15 +125,7 @@ def cpu_baseline(config: int, wl, nr: int, nz: int, max_cores: int = 16):
         per = pool.map(_oracle_series, [(config, b) for b in range(nser)])
     wall = time.perf_counter() - t0
     cells = nser * nr * nz
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
+    model = _cpu_model()
     return {"value": cells / wall, "unit": "cells/s", "cores": nser, "kind": "oracle",
             "sample": f"{nser} of {wl.nseries} series of the same workload, one oracle process per "
                       f"series, full plane + harmonic sums + candidates in FP64 "
@@ -182,7 +215,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -223,6 +256,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     fdas.load()
+    if args.config == 4:
+        return bench_ragged(args)
     wl = _workload(args.config)
     print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
     x = torch.from_numpy(synth.generate(wl)).cuda()
@@ -327,6 +362,133 @@ def main():
         "plain_path": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "candidates": int(len(cands)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def plane_flops(nseries, nsamp, rlo, nz, L, mseg):
+    """Algorithmic FLOPs of the overlap-save plane: per (z row, parity, segment) an inverse
+    FFT (5 L log2 L), the template product (6 L) and the power (3 L); per segment and z
+    group one forward FFT and the scaling."""
+    Lv = L - 2 * mseg
+    nseg = math.ceil((nsamp // 2 - rlo) / Lv)
+    G = 1
+    while G < 8 and nz >= 2 * G * 12:
+        G *= 2
+    return nseries * nseg * (2 * nz * (5 * L * math.log2(L) + 9 * L) + G * (5 * L * math.log2(L) + 2 * L))
+
+
+def bench_ragged(args):
+    """Uneven batch: 512 series of 2^16..2^20 samples with per-series zmax in one
+    fdas_search_ragged call (graph replay, autotuned launch parameters), against
+    the plain path (one fdas_search call per series, default parameters)."""
+    import numpy as np
+    import torch
+
+    import paper_1912_12807_amd as fdas
+    import synth
+
+    wl = _workload(4)
+    print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
+    offs = wl.offsets()
+    buf = torch.from_numpy(synth.generate_ragged(wl)).cuda()
+    geo = [fdas.geometry(wl.nsamp[b], wl.tsamp[b], wl.zmax[b], wl.dz) for b in range(wl.nseries)]
+    cells_of = [nr * nz for _, nr, nz in geo]
+    cells = float(sum(cells_of))
+    nmax, zmax = max(wl.nsamp), max(wl.zmax)
+    run = dict(sigma=wl.sigma, cap=1 << 21)
+
+    def call(plan):
+        return plan.search_ragged(buf, offs, wl.nsamp, wl.tsamp, wl.zmax, **run)
+
+    def timed(plan, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            c = call(plan)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, c
+
+    plan = fdas.Plan(nmax, wl.nseries, zmax, wl.dz, wl.numharm, autotune=1, graph=1)
+    print(f"[bench] warmup {args.warmup} (autotune, graph capture)", file=sys.stderr, flush=True)
+    for _ in range(max(1, args.warmup)):
+        cands = call(plan)
+    tuning = plan.tuning()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    sec, cands = timed(plan, args.steps)
+    value = cells / sec
+
+    # same launches eagerly with phase events: kernel times for the roofline
+    prof = fdas.Plan(nmax, wl.nseries, zmax, wl.dz, wl.numharm, profile=1)
+    prof.load_tuning(tuning)
+    call(prof)
+    prof.profile(reset=True)
+    pe_sec, cands_eager = timed(prof, 2)
+    ph = prof.profile(reset=True)
+    assert np.array_equal(cands, cands_eager), "graph replay and eager launches disagree"
+    prof.close()
+    cfg = {}
+    for line in tuning.split("\n"):
+        f = line.split()
+        if f:
+            cfg[(int(f[0]), int(f[1]))] = (int(f[3]), int(f[4]), int(f[5]))
+    flops = 0.0
+    for b in range(wl.nseries):
+        rlo, nr, nz = geo[b]
+        L = cfg[(wl.nsamp[b], nz // 2)][0]
+        mseg = int(math.ceil(wl.zmax[b] / 2 - 1e-9)) + 16
+        flops += plane_flops(1, wl.nsamp[b], rlo, nz, L, mseg)
+    k4_s = ph["plane"][0] / 1e3 / 2
+    achieved = flops / k4_s / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK, "kernel": DOMINANT["plane"],
+            "per_unit": f"{flops / cells:.1f} FLOP/cell (summed over the launches of all groups)",
+            "traffic": measured_traffic("plane", wl.name), "launch_ms": 1e3 * k4_s / (ph["plane"][1] / 2),
+            "launches_per_step": ph["plane"][1] // 2}
+
+    # grouped launches with default parameters, no graph
+    base = fdas.Plan(nmax, wl.nseries, zmax, wl.dz, wl.numharm)
+    call(base)
+    b_sec, _ = timed(base, max(1, args.steps // 2))
+    base.close()
+
+    plain = None
+    if not args.no_plain:
+        print("[bench] plain per-series path", file=sys.stderr, flush=True)
+        p1 = fdas.Plan(nmax, 1, zmax, wl.dz, wl.numharm)
+        views = [buf[offs[b]:offs[b] + wl.nsamp[b]].view(1, -1) for b in range(wl.nseries)]
+        p1.search(views[0], wl.tsamp[0], zmax=wl.zmax[0], **run)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(wl.nseries):
+            p1.search(views[b], wl.tsamp[b], zmax=wl.zmax[b], **run)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        plain = {"value": cells / pw, "unit": "cells/s", "ms_per_step": 1e3 * pw,
+                 "what": "same kernels, one fdas_search call per series, default launch parameters"}
+        p1.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_ragged(4, wl, cells_of)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "nseries": wl.nseries, "nsamp": "2^16..2^20 (per series)",
+                   "tobs_s": 52.4288, "zmax": "0/50/100/200/300 (per series)", "dz": wl.dz,
+                   "numharm": wl.numharm, "sigma": wl.sigma, "cells_per_step": cells,
+                   "groups": len(cfg), "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_path": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "grouped_default_eager": {"value": cells / b_sec, "ms_per_step": 1e3 * b_sec},
+        "phases_ms": {k: round(v[0] / 2, 4) for k, v in ph.items()},
+        "tuning": tuning.strip().split("\n"),
         "candidates": int(len(cands)),
     }
     print(json.dumps(out), flush=True)

@@ -68,7 +68,14 @@ typedef struct {
     int32_t harm_block;          /* drift rows per bound block (0 = automatic) */
     int32_t harm_pair;           /* 0: block maxima per bin, covering both half-bin columns
                                     (default); 1: per column (tighter bound, twice the memory) */
-    int32_t reserved[2];         /* must be zero */
+    int32_t autotune;            /* 1: on the first search of each shape (nsamp, zmax, numharm),
+                                    time candidate seg_len / harm_block / harm_pair on that data
+                                    and keep the fastest (results agree to FP32 rounding) */
+    int32_t graph;               /* 1: fdas_search and fdas_search_ragged capture their launches
+                                    in a hipGraph and replay it when a call with the same input
+                                    pointer and shapes repeats (sigma and offsets may change);
+                                    ignored while profile is set */
+    int32_t reserved[4];         /* must be zero */
 } fdas_plan_opts;
 
 /* One candidate. r = r_idx/2 and z = z_idx*dz are the Fourier frequency
@@ -120,6 +127,31 @@ void fdas_plan_destroy(fdas_plan p);
 fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
                         double tsamp, double zmax, double dz, int32_t numharm, double sigma,
                         fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream);
+
+/* Search a ragged batch: series i (float32, device) starts at series_dev +
+ * offsets[i] (an even element offset) and has nsamp[i] samples taken every
+ * tsamp[i] seconds, searched to drift zmax[i] (a whole multiple of dz; 0 is
+ * allowed). offsets, nsamp, tsamp and zmax are host arrays of nseries
+ * entries; dz, numharm and sigma are common. Series of the same (nsamp,
+ * search band, zmax) are searched together as one batch. Output and errors as
+ * fdas_search (records sorted by (series, harm, r_idx), series = index i);
+ * every nsamp[i] must be at most the plan's max_nsamp, nseries at most its
+ * max_series, and one series' plane must fit the plan's workspace (always
+ * true for zmax[i] up to the plan's zmax). The caller guarantees that every
+ * series lies inside its buffer. A truncated result (FDAS_E_TRUNC) holds the
+ * first cap records of the complete sorted list. */
+fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64_t *offsets,
+                               const int64_t *nsamp, const double *tsamp, const double *zmax,
+                               int32_t nseries, double dz, int32_t numharm, double sigma,
+                               fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream);
+
+/* Autotuner results as text, one line per shape:
+ * "nsamp zsteps numharm seg_len harm_block harm_pair". fdas_tuning_export
+ * writes at most cap bytes (including the terminating NUL) and sets *len to
+ * the full length; fdas_tuning_import adds lines in the same format (a
+ * tuning file kept by the caller), replacing entries of the same shape. */
+fdas_status fdas_tuning_export(fdas_plan p, char *buf, int64_t cap, int64_t *len);
+fdas_status fdas_tuning_import(fdas_plan p, const char *text);
 
 /* The normalised power plane of each series: plane_dev (device, float32)
  * receives [nseries][NZ][NR] with NZ = 2 zmax/dz + 1 rows (z = (row - zmax/dz)

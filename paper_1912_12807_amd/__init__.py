@@ -26,7 +26,7 @@ EXPORTED = (
     "fdas_plan_opts_default", "fdas_plan_create", "fdas_plan_destroy", "fdas_search", "fdas_plane",
     "fdas_harmsum", "fdas_spectrum", "fdas_geometry", "fdas_threshold", "fdas_sigma",
     "fdas_template_taps", "fdas_status_string", "fdas_last_error", "fdas_profile_read",
-    "fdas_plan_get_info",
+    "fdas_plan_get_info", "fdas_search_ragged", "fdas_tuning_export", "fdas_tuning_import",
 )
 PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "argmax", "copyout")
 
@@ -37,7 +37,8 @@ class PlanOpts(ctypes.Structure):
                 ("max_candidates", ctypes.c_int64), ("seg_len", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("harm_order", ctypes.c_int32),
                 ("harm_bound", ctypes.c_int32), ("harm_block", ctypes.c_int32),
-                ("harm_pair", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("harm_pair", ctypes.c_int32), ("autotune", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -109,6 +110,15 @@ def load(path: Optional[str] = None):
     lib.fdas_profile_read.restype = c.c_int
     lib.fdas_plan_get_info.argtypes = [P, c.POINTER(PlanInfo)]
     lib.fdas_plan_get_info.restype = c.c_int
+    lib.fdas_search_ragged.argtypes = [P, P, c.POINTER(c.c_int64), c.POINTER(c.c_int64),
+                                       c.POINTER(c.c_double), c.POINTER(c.c_double), c.c_int32,
+                                       c.c_double, c.c_int32, c.c_double, P, c.c_int64,
+                                       c.POINTER(c.c_int64), P]
+    lib.fdas_search_ragged.restype = c.c_int
+    lib.fdas_tuning_export.argtypes = [P, c.c_char_p, c.c_int64, c.POINTER(c.c_int64)]
+    lib.fdas_tuning_export.restype = c.c_int
+    lib.fdas_tuning_import.argtypes = [P, c.c_char_p]
+    lib.fdas_tuning_import.restype = c.c_int
     _lib = lib
     return lib
 
@@ -191,6 +201,58 @@ class Plan:
         if st != FDAS_OK:
             self._raise(st, "fdas_search")
         return out[:n.value].copy()
+
+    def search_ragged(self, buf, offsets, nsamp, tsamp, zmax, dz: float = None, numharm: int = None,
+                      sigma: float = 6.0, cap: int = 1 << 16, stream=None, allow_trunc: bool = False):
+        """Search a ragged batch packed in one CUDA float32 buffer: series i is
+        buf[offsets[i] : offsets[i] + nsamp[i]] (offsets even), sampled every
+        tsamp[i] s, searched to drift zmax[i]. Candidates as ``search`` with
+        ``series`` = i."""
+        import torch
+        if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.dtype == torch.float32
+                and buf.is_contiguous()):
+            raise TypeError("buf must be a contiguous CUDA float32 tensor")
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        nsamp = np.ascontiguousarray(nsamp, dtype=np.int64)
+        nser = len(offsets)
+        tsamp = np.ascontiguousarray(np.broadcast_to(np.asarray(tsamp, dtype=np.float64), (nser,)))
+        zmax = np.ascontiguousarray(np.broadcast_to(np.asarray(zmax, dtype=np.float64), (nser,)))
+        if len(nsamp) != nser:
+            raise ValueError("offsets and nsamp differ in length")
+        if nser and (np.any(offsets < 0) or np.any(offsets + nsamp > buf.numel())):
+            raise ValueError("a series lies outside the buffer")
+        dz = self.dz if dz is None else dz
+        numharm = self.numharm if numharm is None else numharm
+        out = np.zeros(int(cap), dtype=CAND_DTYPE)
+        n = ctypes.c_int64(0)
+        i64 = ctypes.POINTER(ctypes.c_int64)
+        f64 = ctypes.POINTER(ctypes.c_double)
+        st = self.lib.fdas_search_ragged(self.handle, ctypes.c_void_p(buf.data_ptr()),
+                                         offsets.ctypes.data_as(i64), nsamp.ctypes.data_as(i64),
+                                         tsamp.ctypes.data_as(f64), zmax.ctypes.data_as(f64), nser,
+                                         float(dz), int(numharm), float(sigma),
+                                         out.ctypes.data_as(ctypes.c_void_p), int(cap), ctypes.byref(n),
+                                         _stream_handle(stream))
+        if st == FDAS_E_TRUNC and allow_trunc:
+            return out[:cap], int(n.value)
+        if st != FDAS_OK:
+            self._raise(st, "fdas_search_ragged")
+        return out[:n.value].copy()
+
+    def tuning(self) -> str:
+        """The autotuner's choices as text (one line per shape)."""
+        n = ctypes.c_int64(0)
+        self.lib.fdas_tuning_export(self.handle, None, 0, ctypes.byref(n))
+        buf = ctypes.create_string_buffer(int(n.value) + 1)
+        st = self.lib.fdas_tuning_export(self.handle, buf, len(buf), ctypes.byref(n))
+        if st != FDAS_OK:
+            self._raise(st, "fdas_tuning_export")
+        return buf.value.decode()
+
+    def load_tuning(self, text: str):
+        st = self.lib.fdas_tuning_import(self.handle, text.encode())
+        if st != FDAS_OK:
+            self._raise(st, "fdas_tuning_import")
 
     def harmsum(self, plane, nsamp: int, tsamp: float, zmax: float = None, dz: float = None,
                 numharm: int = None, sigma: float = 6.0, cap: int = 1 << 16, stream=None):

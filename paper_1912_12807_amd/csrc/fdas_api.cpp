@@ -1,11 +1,14 @@
-// C ABI and host runtime: plans, the FP64-built template bank, workspace
-// management and the order in which the search kernels are enqueued.
+// C ABI and host runtime: plans, the FP64-built template banks, workspace
+// management, the autotuner, graph replay and the order in which the search
+// kernels are enqueued.
 //
-// One search enqueues, on the caller's stream:
-//   K1 real FFT of every series -> K2 median normalisation (or a fixed scale)
+// A search is a list of groups of series that share (nsamp, search band,
+// zmax). Each group enqueues, on one stream:
+//   K1 real FFT -> K2 median normalisation (or a fixed scale)
 //   then per chunk of series (sized to the plane workspace):
-//   K4 power plane -> K5 harmonic-sum maxima -> K6 ordered compaction -> argmax
-// and finally copies the record count and the records to pinned host memory,
+//   K4 power plane + drift-block maxima -> K5 harmonic sums -> K6 ordered
+//   compaction -> drift argmax.
+// The record count and the records are then copied to pinned host memory,
 // where the FP64 significance and physical units are attached (the candidate
 // list of the paper's Section 2, step 5).
 #include "fdas_internal.h"
@@ -14,7 +17,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
+#include <list>
+#include <map>
+#include <sstream>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -25,6 +30,8 @@ using namespace fdas;
 namespace {
 
 constexpr int64_t kDefaultCands = 1 << 20;
+constexpr size_t kMaxBanks = 8;
+constexpr size_t kMaxTables = 16;
 
 struct Geometry {
     int64_t nsamp = 0, half = 0, rlo = 0, NR = 0;
@@ -59,6 +66,55 @@ int nstages_of(int numharm) {
     return s + 1;
 }
 bool valid_numharm(int h) { return h == 1 || h == 2 || h == 4 || h == 8 || h == 16 || h == 32; }
+int zgroups_of(int NZ) {
+    int G = 1;
+    while (G < 8 && NZ >= 2 * G * 12) G *= 2;
+    return G;
+}
+int default_block_rows(int numharm) { return numharm <= 8 ? 10 : numharm == 16 ? 8 : 6; }
+constexpr int kMinBlockRows = 4;   // smallest block the autotuner tries (sizes the maxima buffer)
+
+bool seg_len_ok(int L, int mseg) { return pow2(L) && L >= 512 && L <= 4096 && L - 2 * mseg >= 64; }
+
+// Segment length for a half-width: the smallest L with L >= 16 mseg (>= 87.5 %
+// of each segment valid), or the requested one if it leaves >= 64 valid bins.
+int choose_L(int mseg, int requested) {
+    if (requested) return seg_len_ok(requested, mseg) ? requested : 0;
+    for (int L = 512; L <= 4096; L *= 2)
+        if (L >= 16 * mseg) return L;
+    return (4096 - 2 * mseg >= 1024) ? 4096 : 0;
+}
+
+// Tunable launch parameters of one group shape; none of them changes a
+// result beyond FP32 rounding.
+struct LaunchCfg {
+    int L = 0;       // overlap-save segment length
+    int bz = 0;      // drift rows per bound block
+    int pair = 1;    // block maxima per bin (1) or per column (0)
+};
+
+struct Bank {
+    double zmax = -1, dz = -1;
+    int K = 0, L = 0, mseg = 0, NZ = 0;
+    float2 *d = nullptr;
+    uint64_t used = 0;
+};
+
+struct RowTable {
+    int NZ = -1, G = -1, bz = -1, nh = -1;
+    int32_t *d = nullptr;
+    int nblk = 0;
+    uint64_t used = 0;
+};
+
+// One group of a search: series that share nsamp, band and zmax.
+struct Group {
+    Geometry g;
+    double zmax = 0;
+    int nb = 0;              // series in the group
+    int vbase = 0;           // first virtual series id (position in the group-ordered batch)
+    LaunchCfg cfg;
+};
 
 }  // namespace
 
@@ -70,12 +126,12 @@ struct fdas_plan_s {
     fdas_plan_opts opts{};
     std::string last_error;
     bool sticky = false;
+    uint64_t tick = 0;
+    uint64_t call_tick = 0;     // tick at the start of the current call
 
-    // template bank
-    double bank_zmax = -1, bank_dz = -1;
-    int L = 0, mseg = 0, bankNZ = 0;
-    float2 *d_bank = nullptr;
-    size_t bank_bytes = 0;
+    std::list<Bank> banks;      // list: entries keep their address while others are evicted
+    std::list<RowTable> tables;
+    std::map<std::tuple<int64_t, int, int>, LaunchCfg> tuned;   // (nsamp, zsteps, numharm)
 
     // workspace
     int64_t spitch = 0;
@@ -84,9 +140,9 @@ struct fdas_plan_s {
     double *d_norm = nullptr;
     float *d_thr = nullptr;
     int64_t *d_state = nullptr;
+    int64_t *d_offs = nullptr;  // ragged series offsets (complex units), group order
     float *d_plane = nullptr;
     int64_t plane_cap = 0;      // floats
-    int chunk_series = 0;
     float *d_maxv = nullptr;
     int64_t maxv_cap = 0;       // floats
     int32_t *d_counts = nullptr;
@@ -94,25 +150,29 @@ struct fdas_plan_s {
     int64_t nblk_cap = 0;
     DevCand *d_rec = nullptr;
     int64_t rec_cap = 0;
-    // drift-row block maxima for the bounded harmonic sums
     float *d_pyr = nullptr;
     int64_t pyr_cap = 0;        // floats
-    int32_t *d_rb = nullptr;    // lo[nblk + 1] followed by of_row[NZ]
-    int64_t rb_cap = 0;
-    int rb_NZ = -1, rb_G = -1, rb_bz = -1, rb_nh = -1, rb_nblk = 0;
-    int last_harm_blocks = 0, last_harm_pair = 0;   // what the last search's K5 used
+    int last_harm_blocks = 0, last_harm_pair = 0;
+    int last_L = 0, last_mseg = 0, last_NZ = 0;
     // pinned host staging
     int64_t *h_state = nullptr;
-    float *h_small = nullptr;   // thresholds / fixed scales
+    float *h_small = nullptr;   // thresholds
     DevCand *h_rec = nullptr;
     int64_t h_rec_cap = 0;
-    float *h_scale = nullptr;
+    int64_t *h_offs = nullptr;
+
+    // graph replay
+    hipStream_t cap_st = nullptr;   // private stream that captures (never executes) the launches
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    std::string graph_key;
 
     // phase timing (opts.profile)
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev_pending;
     double prof_ms[FDAS_NPHASES] = {0};
     int64_t prof_n[FDAS_NPHASES] = {0};
+    bool capturing = false;
 
     hipEvent_t take_event() {
         if (!ev_pool.empty()) {
@@ -128,7 +188,7 @@ struct fdas_plan_s {
         return e;
     }
     hipEvent_t begin(hipStream_t st) {
-        if (!opts.profile) return nullptr;
+        if (!opts.profile || capturing) return nullptr;
         hipEvent_t e = take_event();
         if (e) (void)hipEventRecord(e, st);
         return e;
@@ -212,23 +272,43 @@ fdas_status halloc(fdas_plan p, T **ptr, int64_t count, const char *what) {
     return FDAS_OK;
 }
 
-int choose_L(int mseg, int requested) {
-    if (requested) return (pow2(requested) && requested >= 512 && requested <= 4096 &&
-                           requested - 2 * mseg >= 64) ? requested : 0;
-    for (int L = 512; L <= 4096; L *= 2)
-        if (L >= 16 * mseg) return L;
-    return (4096 - 2 * mseg >= 1024) ? 4096 : 0;
+void drop_graph(fdas_plan p) {
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    if (p->graph_def) (void)hipGraphDestroy(p->graph_def);
+    p->graph = nullptr;
+    p->graph_def = nullptr;
+    p->graph_key.clear();
 }
 
-// Build (or keep) the bank for (zmax, dz): [NZ][2][L] kernel spectra, FP64 -> float32.
-fdas_status ensure_bank(fdas_plan p, double zmax, double dz) {
-    if (p->d_bank && p->bank_zmax == zmax && p->bank_dz == dz) return FDAS_OK;
+// Evict the least recently used entry of a cache if it is full and that entry
+// was not used by the current call (earlier calls have completed on the device).
+template <typename T>
+void evict(fdas_plan p, std::list<T> &cache, size_t limit, void *(*mem)(T &)) {
+    if (cache.size() < limit) return;
+    auto it = std::min_element(cache.begin(), cache.end(),
+                               [](const T &a, const T &b) { return a.used < b.used; });
+    if (it->used >= p->call_tick) return;
+    (void)hipFree(mem(*it));
+    cache.erase(it);
+    drop_graph(p);
+}
+
+// ---------------------------------------------------------------- template banks
+
+// The bank for (zmax, dz, L): [NZ][2][L] kernel spectra, FP64 -> float32.
+fdas_status get_bank(fdas_plan p, double zmax, double dz, int L, const Bank **out) {
+    const int K = p->opts.K;
+    for (auto &b : p->banks) {
+        if (b.zmax == zmax && b.dz == dz && b.L == L && b.K == K) {
+            b.used = ++p->tick;
+            *out = &b;
+            return FDAS_OK;
+        }
+    }
     const int Z = (int)std::round(zmax / dz);
     const int NZ = 2 * Z + 1;
-    const int K = p->opts.K;
     const int mseg = half_width(Z * dz, K);
-    const int L = choose_L(mseg, p->opts.seg_len);
-    if (!L) return p->fail(FDAS_E_UNSUPPORTED, "zmax too large for the supported segment lengths");
+    if (!seg_len_ok(L, mseg)) return p->fail(FDAS_E_UNSUPPORTED, "segment length too short for zmax");
     std::vector<float> host((size_t)NZ * 2 * L * 2);
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
@@ -241,155 +321,272 @@ fdas_status ensure_bank(fdas_plan p, double zmax, double dz) {
         });
     }
     for (auto &t : pool) t.join();
-    const size_t bytes = host.size() * sizeof(float);
-    if (bytes > p->bank_bytes) {
-        TRY(dalloc(p, &p->d_bank, (int64_t)(host.size() / 2), "template bank"));
-        p->bank_bytes = bytes;
+    evict<Bank>(p, p->banks, kMaxBanks, [](Bank &b) -> void * { return b.d; });
+    Bank b;
+    b.zmax = zmax;
+    b.dz = dz;
+    b.K = K;
+    b.L = L;
+    b.mseg = mseg;
+    b.NZ = NZ;
+    TRY(dalloc(p, &b.d, (int64_t)(host.size() / 2), "template bank"));
+    if (hipMemcpy(b.d, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        const hipError_t e = hipGetLastError();
+        (void)hipFree(b.d);
+        return p->hip(e == hipSuccess ? hipErrorUnknown : e, "template bank upload");
     }
-    HIPTRY(p, hipMemcpy(p->d_bank, host.data(), bytes, hipMemcpyHostToDevice));
-    p->bank_zmax = zmax;
-    p->bank_dz = dz;
-    p->L = L;
-    p->mseg = mseg;
-    p->bankNZ = NZ;
+    b.used = ++p->tick;
+    p->banks.push_back(b);
+    *out = &p->banks.back();
     return FDAS_OK;
 }
 
-fdas_status check_common(fdas_plan p, const void *dev, int64_t nsamp, int32_t nseries,
-                         double tsamp, double zmax, double dz, Geometry &g) {
-    if (!p) return FDAS_E_INVAL;
-    if (p->sticky) return p->fail(FDAS_E_DEVICE, "plan is in a failed state: " + p->last_error);
-    if (!dev || ((uintptr_t)dev & 7)) return p->fail(FDAS_E_INVAL, "device pointer NULL or not 8-byte aligned");
-    if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
-    if (nsamp > p->max_nsamp) return p->fail(FDAS_E_INVAL, "nsamp exceeds the plan's max_nsamp");
-    fdas_status s = geometry(nsamp, tsamp, zmax, dz, p->opts.flo_hz, g);
-    if (s != FDAS_OK) return p->fail(s, "invalid nsamp/tsamp/zmax/dz (odd nsamp, zmax not a multiple of dz, or empty band)");
-    if (!pow2(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp must be a power of two");
-    int dev_now = -1;
-    if (hipGetDevice(&dev_now) != hipSuccess || dev_now != p->device)
-        return p->fail(FDAS_E_INVAL, "current HIP device differs from the plan's device");
-    return FDAS_OK;
-}
-
-// K1 + K2 for the batch; leaves spectra in d_spec and scales in d_scale.
-fdas_status run_spectrum(fdas_plan p, const float *x, const Geometry &g, int nseries, hipStream_t st) {
-    hipEvent_t e = p->begin(st);
-    HIPTRY(p, launch_rfft(x, g.nsamp, nseries, p->d_w0, p->d_w1, p->d_spec, p->spitch, st));
-    p->end(0, e, st);
-    if (p->opts.norm == FDAS_NORM_MEDIAN) {
-        e = p->begin(st);
-        HIPTRY(p, launch_median_scale(p->d_spec, p->spitch, g.half, nseries, p->d_scale, p->d_norm, st));
-        p->end(1, e, st);
-    } else {
-        const double nrm = (double)g.nsamp * p->opts.fixed_var;
-        for (int b = 0; b < nseries; ++b) p->h_scale[b] = (float)std::sqrt(1.0 / nrm);
-        HIPTRY(p, hipMemcpyAsync(p->d_scale, p->h_scale, nseries * sizeof(float), hipMemcpyHostToDevice, st));
-    }
-    return FDAS_OK;
-}
-
-CorrGeom corr_geom(fdas_plan p, const Geometry &g) {
-    CorrGeom c;
-    c.L = p->L;
-    c.mseg = p->mseg;
-    c.Lv = p->L - 2 * p->mseg;
-    c.half = g.half;
-    c.rlo = g.rlo;
-    c.nseg = (int)((g.half - g.rlo + c.Lv - 1) / c.Lv);
-    c.NZ = g.NZ;
-    int G = 1;
-    while (G < 8 && g.NZ >= 2 * G * 12) G *= 2;
-    c.zgroups = G;
-    return c;
-}
-
-int block_rows(fdas_plan p, int numharm) {
-    if (p->opts.harm_block) return p->opts.harm_block;
-    return numharm <= 8 ? 10 : numharm == 16 ? 8 : 6;
-}
-
-// Row-block tables for the bounded harmonic sums (cached per geometry):
+// Row-block tables for the bounded harmonic sums, cached per geometry:
 // lo[nblk + 1], of_row[NZ], frange[nblk][numharm] in one device buffer.
-fdas_status ensure_row_blocks(fdas_plan p, int NZ, int G, int bz, int numharm, RowBlocks &rb) {
-    if (!(p->d_rb && p->rb_NZ == NZ && p->rb_G == G && p->rb_bz == bz && p->rb_nh == numharm)) {
+fdas_status get_rows(fdas_plan p, int NZ, int G, int bz, int numharm, bool pair, RowBlocks &rb) {
+    RowTable *t = nullptr;
+    for (auto &x : p->tables)
+        if (x.NZ == NZ && x.G == G && x.bz == bz && x.nh == numharm) t = &x;
+    if (!t) {
         std::vector<int32_t> lo, of_row, fr;
         row_blocks(NZ, G, bz, lo, of_row);
         fraction_ranges(NZ, numharm, lo, of_row, fr);
         std::vector<int32_t> all(lo);
         all.insert(all.end(), of_row.begin(), of_row.end());
         all.insert(all.end(), fr.begin(), fr.end());
-        const int64_t n = (int64_t)all.size();
-        if (n > p->rb_cap) {
-            TRY(dalloc(p, &p->d_rb, n, "row-block tables"));
-            p->rb_cap = n;
+        evict<RowTable>(p, p->tables, kMaxTables, [](RowTable &r) -> void * { return r.d; });
+        RowTable n;
+        n.NZ = NZ;
+        n.G = G;
+        n.bz = bz;
+        n.nh = numharm;
+        n.nblk = (int)lo.size() - 1;
+        TRY(dalloc(p, &n.d, (int64_t)all.size(), "row-block tables"));
+        if (hipMemcpy(n.d, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+            const hipError_t e = hipGetLastError();
+            (void)hipFree(n.d);
+            return p->hip(e == hipSuccess ? hipErrorUnknown : e, "row-block table upload");
         }
-        HIPTRY(p, hipMemcpy(p->d_rb, all.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
-        p->rb_NZ = NZ;
-        p->rb_G = G;
-        p->rb_bz = bz;
-        p->rb_nh = numharm;
-        p->rb_nblk = (int)lo.size() - 1;
+        p->tables.push_back(n);
+        t = &p->tables.back();
     }
-    rb.lo = p->d_rb;
-    rb.of_row = p->d_rb + p->rb_nblk + 1;
+    t->used = ++p->tick;
+    rb.lo = t->d;
+    rb.of_row = t->d + t->nblk + 1;
     rb.frange = rb.of_row + NZ;
-    rb.nblk = p->rb_nblk;
+    rb.nblk = t->nblk;
     rb.frange_nh = numharm;
-    rb.pair = p->opts.harm_pair == 0;   // default: maxima per bin (pair); 1 selects per column
+    rb.pair = pair;
     return FDAS_OK;
 }
 
-// K5 + K6 + argmax for one chunk of planes.
-fdas_status run_harm_chunk(fdas_plan p, const float *plane, int64_t pitch, int64_t sstride,
-                           const Geometry &g, int numharm, int b0, int nb, hipStream_t st,
-                           const float *pyr = nullptr, int64_t psstride = 0,
-                           const RowBlocks *rb = nullptr) {
+LaunchCfg default_cfg(fdas_plan p, int Z, double dz, int numharm) {
+    LaunchCfg c;
+    c.L = choose_L(half_width(Z * dz, p->opts.K), p->opts.seg_len);
+    c.bz = p->opts.harm_block ? p->opts.harm_block : default_block_rows(numharm);
+    c.pair = p->opts.harm_pair == 0 ? 1 : 0;
+    return c;
+}
+
+CorrGeom corr_geom(const Bank &bk, const Geometry &g) {
+    CorrGeom c;
+    c.L = bk.L;
+    c.mseg = bk.mseg;
+    c.Lv = bk.L - 2 * bk.mseg;
+    c.half = g.half;
+    c.rlo = g.rlo;
+    c.nseg = (int)((g.half - g.rlo + c.Lv - 1) / c.Lv);
+    c.NZ = g.NZ;
+    c.zgroups = zgroups_of(g.NZ);
+    return c;
+}
+
+// ---------------------------------------------------------------- enqueue helpers
+
+// K1 + K2 for nb series (series b at x + b nsamp, or at x + 2 offs[b] floats).
+fdas_status run_spectrum(fdas_plan p, const float *x, const int64_t *offs, const Geometry &g, int nb,
+                         hipStream_t st) {
+    hipEvent_t e = p->begin(st);
+    HIPTRY(p, launch_rfft(x, g.nsamp, nb, p->d_w0, p->d_w1, p->d_spec, p->spitch, st, offs));
+    p->end(0, e, st);
+    if (p->opts.norm == FDAS_NORM_MEDIAN) {
+        e = p->begin(st);
+        HIPTRY(p, launch_median_scale(p->d_spec, p->spitch, g.half, nb, p->d_scale, p->d_norm, st));
+        p->end(1, e, st);
+    } else {
+        const float sc = (float)std::sqrt(1.0 / ((double)g.nsamp * p->opts.fixed_var));
+        HIPTRY(p, launch_fill_scale(p->d_scale, nb, sc, st));
+    }
+    return FDAS_OK;
+}
+
+// K4 [+ K5 + K6 + argmax] for the nb series whose spectra are in d_spec, in
+// chunks that the workspace holds. timing_only stops after K5 (autotuner).
+fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const LaunchCfg &cfg,
+                       int numharm, int nb, int vbase, bool timing_only, hipStream_t st) {
+    const CorrGeom cg = corr_geom(bk, g);
+    const int64_t pitch = round_up(g.NR, 64);
+    const int64_t sstride = (int64_t)g.NZ * pitch;
+    RowBlocks rb;
+    TRY(get_rows(p, g.NZ, cg.zgroups, cfg.bz, numharm, cfg.pair != 0, rb));
+    const bool bounded = !p->opts.harm_bound && bounded_lds_bytes(rb.nblk, numharm) <= kBoundLdsMax;
+    const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? pitch / 2 : pitch);
     const int NS = nstages_of(numharm);
     const int64_t mpitch = round_up(g.NR, 16);
-    hipEvent_t e = p->begin(st);
-    if (pyr) {
-        HIPTRY(p, launch_harmsum_bounded(plane, pitch, sstride, pyr, psstride, *rb, g.NR, g.rlo, g.Z,
-                                         numharm, nb, p->d_thr, p->d_maxv, mpitch, st));
-    } else {
-        const int order = p->opts.harm_order ? p->opts.harm_order : 1;
-        HIPTRY(p, launch_harmsum(plane, pitch, sstride, g.NR, g.rlo, g.Z, numharm, nb, p->d_maxv, mpitch,
-                                 order, st));
+    int64_t chunk = std::min<int64_t>(p->plane_cap / sstride, p->maxv_cap / (NS * mpitch));
+    chunk = std::min<int64_t>(chunk, p->pyr_cap / psstride);
+    if (chunk < 1) return p->fail(FDAS_E_INVAL, "one series' plane exceeds the workspace");
+    p->last_harm_blocks = bounded ? rb.nblk : 0;
+    p->last_harm_pair = rb.pair ? 1 : 0;
+    p->last_L = bk.L;
+    p->last_mseg = bk.mseg;
+    p->last_NZ = g.NZ;
+    for (int b0 = 0; b0 < nb; b0 += (int)chunk) {
+        const int n = (int)std::min<int64_t>(chunk, nb - b0);
+        hipEvent_t e = p->begin(st);
+        HIPTRY(p, launch_corr_power(p->d_spec + (int64_t)b0 * p->spitch, p->spitch, p->d_scale + b0, bk.d, cg,
+                                    n, p->d_plane, pitch, sstride, p->d_pyr, psstride, rb, st));
+        p->end(2, e, st);
+        e = p->begin(st);
+        if (bounded) {
+            HIPTRY(p, launch_harmsum_bounded(p->d_plane, pitch, sstride, p->d_pyr, psstride, rb, g.NR, g.rlo,
+                                             g.Z, numharm, n, p->d_thr, p->d_maxv, mpitch, st));
+        } else {
+            const int order = p->opts.harm_order ? p->opts.harm_order : 1;
+            HIPTRY(p, launch_harmsum(p->d_plane, pitch, sstride, g.NR, g.rlo, g.Z, numharm, n, p->d_maxv,
+                                     mpitch, order, st));
+        }
+        p->end(3, e, st);
+        if (timing_only) continue;
+        e = p->begin(st);
+        HIPTRY(p, launch_compact(p->d_maxv, (int64_t)n * NS * mpitch, mpitch, NS, vbase + b0, p->d_thr,
+                                 p->d_counts, p->d_offsets, p->d_state, p->d_rec, p->rec_cap, st));
+        p->end(4, e, st);
+        e = p->begin(st);
+        HIPTRY(p, launch_argmax(p->d_plane, pitch, sstride, g.rlo, g.Z, numharm, vbase + b0, p->d_rec,
+                                p->d_state, p->rec_cap, st));
+        p->end(5, e, st);
     }
-    p->end(3, e, st);
-    const int64_t nelem = (int64_t)nb * NS * mpitch;
-    e = p->begin(st);
-    HIPTRY(p, launch_compact(p->d_maxv, nelem, mpitch, NS, b0, p->d_thr, p->d_counts, p->d_offsets,
-                             p->d_state, p->d_rec, p->rec_cap, st));
-    p->end(4, e, st);
-    e = p->begin(st);
-    HIPTRY(p, launch_argmax(plane, pitch, sstride, g.rlo, g.Z, numharm, b0, p->d_rec, p->d_state,
-                            p->rec_cap, st));
-    p->end(5, e, st);
     return FDAS_OK;
 }
 
-fdas_status prepare_harm(fdas_plan p, const Geometry &g, int numharm, double sigma, hipStream_t st) {
+fdas_status upload_thresholds(fdas_plan p, int numharm, double sigma, hipStream_t st) {
     const int NS = nstages_of(numharm);
     for (int s = 0; s < NS; ++s) p->h_small[s] = (float)threshold(1 << s, sigma);
     HIPTRY(p, hipMemcpyAsync(p->d_thr, p->h_small, NS * sizeof(float), hipMemcpyHostToDevice, st));
-    HIPTRY(p, hipMemsetAsync(p->d_state, 0, 2 * sizeof(int64_t), st));
-    (void)g;
     return FDAS_OK;
 }
 
-fdas_status finish(fdas_plan p, const Geometry &g, int numharm, double dz, fdas_cand *out, int64_t cap,
-                   int64_t *n_total, hipStream_t st, bool *need_regrow) {
+// ---------------------------------------------------------------- autotuner
+
+// Launch parameters for a group: the plan's options, a tuned entry for the
+// shape, or (autotune) the fastest candidate timed on the group's first series
+// (K4 + K5 only; spectra of the sample are computed first).
+fdas_status group_cfg(fdas_plan p, const Geometry &g, double zmax, double dz, int numharm, const float *x,
+                      const int64_t *offs, int nb, hipStream_t st, LaunchCfg *out) {
+    const LaunchCfg base = default_cfg(p, g.Z, dz, numharm);
+    if (!base.L) return p->fail(FDAS_E_UNSUPPORTED, "zmax too large for the supported segment lengths");
+    *out = base;
+    const int mseg = half_width(g.Z * dz, p->opts.K);
+    const auto key = std::make_tuple(g.nsamp, g.Z, numharm);
+    auto it = p->tuned.find(key);
+    if (it != p->tuned.end() && seg_len_ok(it->second.L, mseg) && it->second.bz >= 1) {
+        *out = it->second;
+        return FDAS_OK;
+    }
+    if (!p->opts.autotune) return FDAS_OK;
+    std::vector<int> Ls;
+    for (int L = 512; L <= 4096; L *= 2)
+        if (seg_len_ok(L, mseg) && L >= 4 * mseg && (p->opts.seg_len == 0 || L == p->opts.seg_len))
+            Ls.push_back(L);
+    if (Ls.empty()) Ls.push_back(base.L);
+    std::vector<int> bzs;
+    if (p->opts.harm_block) bzs = {p->opts.harm_block};
+    else if (numharm <= 8) bzs = {6, 8, 10, 12, 16};
+    else if (numharm == 16) bzs = {4, 6, 8, 10};
+    else bzs = {4, 6, 8};
+    const int sample = std::min<int>(nb, std::max<int64_t>(8, ((int64_t)1 << 21) / g.nsamp));
+    TRY(run_spectrum(p, x, offs, g, sample, st));
+    hipEvent_t a = p->take_event(), b = p->take_event();
+    if (!a || !b) return p->fail(FDAS_E_DEVICE, "event creation failed");
+    auto time_cfg = [&](const LaunchCfg &c, float *ms) -> fdas_status {
+        const Bank *bk = nullptr;
+        TRY(get_bank(p, zmax, dz, c.L, &bk));
+        TRY(run_chunks(p, g, *bk, c, numharm, sample, 0, true, st));   // warm
+        HIPTRY(p, hipEventRecord(a, st));
+        TRY(run_chunks(p, g, *bk, c, numharm, sample, 0, true, st));
+        HIPTRY(p, hipEventRecord(b, st));
+        HIPTRY(p, hipEventSynchronize(b));
+        HIPTRY(p, hipEventElapsedTime(ms, a, b));
+        return FDAS_OK;
+    };
+    const int32_t was_profile = p->opts.profile;
+    p->opts.profile = 0;
+    LaunchCfg best = base;
+    float best_ms = 3.0e38f;
+    fdas_status s = FDAS_OK;
+    // segment length first (default blocks), then block rows x granularity
+    for (int L : Ls) {
+        LaunchCfg c = base;
+        c.L = L;
+        float ms = 0;
+        if ((s = time_cfg(c, &ms)) != FDAS_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    const LaunchCfg lbest = best;
+    for (size_t i = 0; s == FDAS_OK && i < bzs.size(); ++i) {
+        for (int pair : {1, 0}) {
+            if (p->opts.harm_pair && pair) continue;
+            LaunchCfg c = lbest;
+            c.bz = bzs[i];
+            c.pair = pair;
+            if (c.bz == lbest.bz && c.pair == lbest.pair) continue;
+            float ms = 0;
+            if ((s = time_cfg(c, &ms)) != FDAS_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    }
+    p->opts.profile = was_profile;
+    p->ev_pool.push_back(a);
+    p->ev_pool.push_back(b);
+    TRY(s);
+    p->tuned[key] = best;
+    *out = best;
+    return FDAS_OK;
+}
+
+// ---------------------------------------------------------------- search driver
+
+struct Batch {
+    std::vector<Group> groups;
+    std::vector<int> vmap;      // virtual id -> caller's series index
+    std::vector<int> vgroup;    // virtual id -> group
+    std::vector<double> vT;     // virtual id -> observation length (s)
+};
+
+// Copy the records of a finished search to the host, attach units, and write
+// the first cap records in (series, harm, r_idx) order. need_regrow is set
+// when the device buffer could not hold the records the output requires.
+fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device, fdas_cand *out,
+                   int64_t cap, int64_t *n_total, hipStream_t st, bool *need_regrow) {
     hipEvent_t e = p->begin(st);
     HIPTRY(p, hipMemcpyAsync(p->h_state, p->d_state, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     p->end(6, e, st);
     HIPTRY(p, hipStreamSynchronize(st));
     const int64_t total = p->h_state[0];
     *need_regrow = false;
-    if (total > p->rec_cap && cap > p->rec_cap) {
+    const int64_t n = sorted_on_device ? std::min(total, cap) : total;
+    if (n > p->rec_cap) {
         *need_regrow = true;
+        p->collect();
         return FDAS_OK;
     }
-    const int64_t n = std::min<int64_t>(std::min<int64_t>(total, cap), p->rec_cap);
     if (n > 0) {
         if (n > p->h_rec_cap) {
             TRY(halloc(p, &p->h_rec, n, "candidate staging"));
@@ -401,32 +598,166 @@ fdas_status finish(fdas_plan p, const Geometry &g, int numharm, double dz, fdas_
         HIPTRY(p, hipStreamSynchronize(st));
     }
     p->collect();
+    std::vector<fdas_cand> all;
+    fdas_cand *dst = out;
+    if (!sorted_on_device) {
+        all.resize((size_t)n);
+        dst = all.data();
+    }
     for (int64_t i = 0; i < n; ++i) {
         const DevCand &d = p->h_rec[i];
+        if (d.b < 0 || d.b >= (int)B.vmap.size() || d.s < 0 || d.s > 5)
+            return p->fail(FDAS_E_DEVICE, "internal error: candidate of an unknown series or stage");
+        const Geometry &g = B.groups[B.vgroup[d.b]].g;
         if (d.zq < -g.Z || d.zq > g.Z)
             return p->fail(FDAS_E_DEVICE, "internal error: candidate without a maximising drift");
-        const int H = 1 << d.s;
-        fdas_cand &c = out[i];
-        c.series = d.b;
-        c.harm = H;
-        c.r_idx = (int64_t)d.c + 2 * g.rlo;
-        c.z_idx = d.zq;
-        c.power = d.power;
-        c.sigma = sigma_of(H, (double)d.power);
-        c.r_fund = (double)c.r_idx / (2.0 * H);
-        c.z_fund = (double)d.zq * dz / H;
-        c.f_hz = c.r_fund / g.T;
-        c.fdot_hz_s = c.z_fund / (g.T * g.T);
+    }
+    // units and FP64 significance, over host threads for long lists
+    auto convert = [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const DevCand &d = p->h_rec[i];
+            const Geometry &g = B.groups[B.vgroup[d.b]].g;
+            const int H = 1 << d.s;
+            const double T = B.vT[d.b];
+            fdas_cand &c = dst[i];
+            c.series = B.vmap[d.b];
+            c.harm = H;
+            c.r_idx = (int64_t)d.c + 2 * g.rlo;
+            c.z_idx = d.zq;
+            c.power = d.power;
+            c.sigma = sigma_of(H, (double)d.power);
+            c.r_fund = (double)c.r_idx / (2.0 * H);
+            c.z_fund = (double)d.zq * dz / H;
+            c.f_hz = c.r_fund / T;
+            c.fdot_hz_s = c.z_fund / (T * T);
+        }
+    };
+    const int64_t per_thread = 2048;
+    const int nth = (int)std::min<int64_t>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
+                                           (n + per_thread - 1) / per_thread);
+    if (nth <= 1) {
+        convert(0, n);
+    } else {
+        std::vector<std::thread> pool;
+        for (int w = 0; w < nth; ++w) pool.emplace_back(convert, n * w / nth, n * (w + 1) / nth);
+        for (auto &t : pool) t.join();
+    }
+    if (!sorted_on_device) {
+        std::stable_sort(all.begin(), all.end(), [](const fdas_cand &a, const fdas_cand &b) {
+            if (a.series != b.series) return a.series < b.series;
+            if (a.harm != b.harm) return a.harm < b.harm;
+            return a.r_idx < b.r_idx;
+        });
+        const int64_t m = std::min<int64_t>(cap, n);
+        if (m > 0) std::memcpy(out, all.data(), (size_t)m * sizeof(fdas_cand));
     }
     *n_total = total;
-    (void)numharm;
     return total > cap ? FDAS_E_TRUNC : FDAS_OK;
 }
 
-fdas_status grow_records(fdas_plan p, int64_t n) {
-    TRY(dalloc(p, &p->d_rec, n, "candidate records"));
-    p->rec_cap = n;
+// Enqueue every group of a batch on st.
+fdas_status enqueue_groups(fdas_plan p, const float *x, bool ragged, const Batch &B, double dz, int numharm,
+                           hipStream_t st) {
+    HIPTRY(p, launch_zero_state(p->d_state, st));
+    for (const auto &G : B.groups) {
+        const Bank *bk = nullptr;
+        TRY(get_bank(p, G.zmax, dz, G.cfg.L, &bk));
+        TRY(run_spectrum(p, x, ragged ? p->d_offs + G.vbase : nullptr, G.g, G.nb, st));
+        TRY(run_chunks(p, G.g, *bk, G.cfg, numharm, G.nb, G.vbase, false, st));
+    }
     return FDAS_OK;
+}
+
+// Run a prepared batch (thresholds and offsets already uploaded on st), eagerly
+// or by replaying a captured graph, and collect the records; the device record
+// buffer grows once if it was too small.
+fdas_status run_batch(fdas_plan p, const float *x, bool ragged, const Batch &B, double dz, int numharm,
+                      const std::string &key, fdas_cand *out, int64_t cap, int64_t *n_total, hipStream_t st) {
+    const bool use_graph = p->opts.graph && !p->opts.profile;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (use_graph) {
+            if (p->graph_key != key || !p->graph) {
+                drop_graph(p);
+                if (!p->cap_st) HIPTRY(p, hipStreamCreateWithFlags(&p->cap_st, hipStreamNonBlocking));
+                // every bank and table of the batch must exist before capture
+                for (const auto &G : B.groups) {
+                    const Bank *bk = nullptr;
+                    TRY(get_bank(p, G.zmax, dz, G.cfg.L, &bk));
+                    RowBlocks rb;
+                    TRY(get_rows(p, G.g.NZ, zgroups_of(G.g.NZ), G.cfg.bz, numharm, G.cfg.pair != 0, rb));
+                }
+                HIPTRY(p, hipStreamBeginCapture(p->cap_st, hipStreamCaptureModeThreadLocal));
+                p->capturing = true;
+                const fdas_status s = enqueue_groups(p, x, ragged, B, dz, numharm, p->cap_st);
+                p->capturing = false;
+                hipGraph_t gdef = nullptr;
+                const hipError_t e = hipStreamEndCapture(p->cap_st, &gdef);
+                if (s != FDAS_OK) {
+                    if (gdef) (void)hipGraphDestroy(gdef);
+                    return s;
+                }
+                HIPTRY(p, e);
+                p->graph_def = gdef;
+                HIPTRY(p, hipGraphInstantiate(&p->graph, gdef, nullptr, nullptr, 0));
+                p->graph_key = key;
+            }
+            HIPTRY(p, hipGraphLaunch(p->graph, st));
+        } else {
+            TRY(enqueue_groups(p, x, ragged, B, dz, numharm, st));
+        }
+        bool regrow = false;
+        const fdas_status s = finish(p, B, dz, !ragged, out, cap, n_total, st, &regrow);
+        if (!regrow) return s;
+        const int64_t need = ragged ? p->h_state[0] : std::min<int64_t>(p->h_state[0], cap);
+        TRY(dalloc(p, &p->d_rec, need, "candidate records"));
+        p->rec_cap = need;
+        drop_graph(p);
+    }
+    return p->fail(FDAS_E_DEVICE, "internal error: candidate capacity did not converge");
+}
+
+fdas_status check_plan(fdas_plan p) {
+    if (!p) return FDAS_E_INVAL;
+    if (p->sticky) return p->fail(FDAS_E_DEVICE, "plan is in a failed state: " + p->last_error);
+    int dev_now = -1;
+    if (hipGetDevice(&dev_now) != hipSuccess || dev_now != p->device)
+        return p->fail(FDAS_E_INVAL, "current HIP device differs from the plan's device");
+    p->call_tick = p->tick + 1;
+    return FDAS_OK;
+}
+
+fdas_status check_common(fdas_plan p, const void *dev, int64_t nsamp, int32_t nseries,
+                         double tsamp, double zmax, double dz, Geometry &g) {
+    TRY(check_plan(p));
+    if (!dev || ((uintptr_t)dev & 7)) return p->fail(FDAS_E_INVAL, "device pointer NULL or not 8-byte aligned");
+    if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
+    if (nsamp > p->max_nsamp) return p->fail(FDAS_E_INVAL, "nsamp exceeds the plan's max_nsamp");
+    fdas_status s = geometry(nsamp, tsamp, zmax, dz, p->opts.flo_hz, g);
+    if (s != FDAS_OK) return p->fail(s, "invalid nsamp/tsamp/zmax/dz (odd nsamp, zmax not a multiple of dz, or empty band)");
+    if (!pow2(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp must be a power of two");
+    return FDAS_OK;
+}
+
+fdas_status check_search(fdas_plan p, int32_t numharm, double sigma, fdas_cand *out, int64_t cap,
+                         int64_t *n_total) {
+    if (!valid_numharm(numharm) || numharm > p->max_numharm)
+        return p->fail(FDAS_E_INVAL, "numharm must be a power of two up to the plan's numharm");
+    if (!(sigma > 0) || !std::isfinite(sigma)) return p->fail(FDAS_E_INVAL, "sigma must be finite and > 0");
+    if (cap < 0 || (cap > 0 && !out) || !n_total) return p->fail(FDAS_E_INVAL, "bad output buffer");
+    return FDAS_OK;
+}
+
+// One series' plane must fit the workspace.
+fdas_status check_fits(fdas_plan p, const Geometry &g) {
+    const int64_t sstride = (int64_t)g.NZ * round_up(g.NR, 64);
+    if (sstride > p->plane_cap)
+        return p->fail(FDAS_E_INVAL, "one series' plane exceeds the workspace; create the plan with this zmax");
+    return FDAS_OK;
+}
+
+void key_group(std::ostringstream &k, const Group &G) {
+    k << '|' << G.g.nsamp << ',' << G.g.rlo << ',' << G.g.Z << ',' << G.nb << ',' << G.cfg.L << ','
+      << G.cfg.bz << ',' << G.cfg.pair;
 }
 
 }  // namespace
@@ -440,9 +771,6 @@ void fdas_plan_opts_default(fdas_plan_opts *o) {
     o->K = 16;
     o->norm = FDAS_NORM_MEDIAN;
     o->fixed_var = 1.0;
-    o->max_workspace_bytes = 0;
-    o->max_candidates = 0;
-    o->seg_len = 0;
 }
 
 const char *fdas_status_string(fdas_status s) {
@@ -481,9 +809,12 @@ void fdas_plan_destroy(fdas_plan p) {
     int cur = -1;
     (void)hipGetDevice(&cur);
     if (p->device >= 0) (void)hipSetDevice(p->device);
-    void *dev[] = {p->d_bank, p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_thr,
-                   p->d_state, p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec,
-                   p->d_pyr, p->d_rb};
+    drop_graph(p);
+    if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
+    for (auto &b : p->banks) (void)hipFree(b.d);
+    for (auto &t : p->tables) (void)hipFree(t.d);
+    void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_thr, p->d_state, p->d_offs,
+                   p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr};
     for (void *q : dev)
         if (q) (void)hipFree(q);
     for (auto &t : p->ev_pending) {
@@ -491,7 +822,7 @@ void fdas_plan_destroy(fdas_plan p) {
         p->ev_pool.push_back(std::get<2>(t));
     }
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-    void *host[] = {p->h_state, p->h_small, p->h_rec, p->h_scale};
+    void *host[] = {p->h_state, p->h_small, p->h_rec, p->h_offs};
     for (void *q : host)
         if (q) (void)hipHostFree(q);
     if (cur >= 0) (void)hipSetDevice(cur);
@@ -505,19 +836,20 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     fdas_plan_opts o;
     fdas_plan_opts_default(&o);
     if (opts) o = *opts;
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
         if (o.reserved[i]) return FDAS_E_INVAL;
     if (max_series < 1 || max_series > 65535 || !valid_numharm(numharm) || o.K < 1 || o.K > 1024 ||
         (o.norm != FDAS_NORM_MEDIAN && o.norm != FDAS_NORM_FIXED) ||
         (o.norm == FDAS_NORM_FIXED && !(o.fixed_var > 0)) || o.max_workspace_bytes < 0 ||
         o.max_candidates < 0 || o.harm_order < 0 || o.harm_order > 3 || o.harm_bound < 0 ||
-        o.harm_bound > 1 || o.harm_block < 0 || o.harm_block > 64 || o.harm_pair < 0 ||
-        o.harm_pair > 1)
+        o.harm_bound > 1 || o.harm_block < 0 || o.harm_block > 64 || o.harm_pair < 0 || o.harm_pair > 1 ||
+        o.autotune < 0 || o.autotune > 1 || o.graph < 0 || o.graph > 1)
         return FDAS_E_INVAL;
     Geometry g;
     if (geometry(max_nsamp, 1e-3, zmax, dz, 0.0, g) != FDAS_OK) return FDAS_E_INVAL;
     if (!pow2(max_nsamp)) return FDAS_E_UNSUPPORTED;
-    if (o.seg_len && !choose_L(half_width(g.Z * dz, o.K), o.seg_len)) return FDAS_E_INVAL;
+    const int mseg = half_width(g.Z * dz, o.K);
+    if (!choose_L(mseg, o.seg_len)) return o.seg_len ? FDAS_E_INVAL : FDAS_E_UNSUPPORTED;
 
     fdas_plan p = new (std::nothrow) fdas_plan_s;
     if (!p) return FDAS_E_NOMEM;
@@ -533,7 +865,8 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
         (void)hipGetLastError();
         return bail(FDAS_E_DEVICE);
     }
-    fdas_status s = ensure_bank(p, zmax, dz);
+    const Bank *bk = nullptr;
+    fdas_status s = get_bank(p, g.Z * dz, dz, default_cfg(p, g.Z, dz, numharm).L, &bk);
     if (s != FDAS_OK) return bail(s);
 
     const int64_t half = max_nsamp / 2;
@@ -545,10 +878,11 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     if ((s = dalloc(p, &p->d_norm, max_series, "norms")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_thr, 8, "thresholds")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_state, 2, "state")) != FDAS_OK) return bail(s);
+    if ((s = dalloc(p, &p->d_offs, max_series, "series offsets")) != FDAS_OK) return bail(s);
 
     // plane workspace: as many series per chunk as the budget allows
-    const int64_t pitch = round_up(max_nsamp, 64);        // >= NR of any search
-    const int64_t per_series = (int64_t)p->bankNZ * pitch;   // floats
+    const int64_t pitch = round_up(max_nsamp, 64);           // >= NR of any search
+    const int64_t per_series = (int64_t)g.NZ * pitch;        // floats
     int64_t budget = o.max_workspace_bytes;
     if (!budget) {
         size_t fr = 0, tot = 0;
@@ -558,17 +892,15 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
         }
         budget = std::min<int64_t>((int64_t)64 << 30, (int64_t)(fr / 2));
     }
-    int64_t chunk = std::min<int64_t>(max_series, budget / (per_series * 4));
+    const int64_t chunk = std::min<int64_t>(max_series, budget / (per_series * 4));
     if (chunk < 1) return bail(FDAS_E_NOMEM);
-    p->chunk_series = (int)chunk;
     p->plane_cap = chunk * per_series;
     if ((s = dalloc(p, &p->d_plane, p->plane_cap, "power plane")) != FDAS_OK) return bail(s);
-    {
-        // block maxima of every chunk series: at most NZ/bz + 8 blocks per series
-        const int bz = block_rows(p, numharm);
-        p->pyr_cap = chunk * (int64_t)(p->bankNZ / bz + 9) * (o.harm_pair == 0 ? pitch / 2 : pitch);
-        if ((s = dalloc(p, &p->d_pyr, p->pyr_cap, "block maxima")) != FDAS_OK) return bail(s);
-    }
+    // block maxima of every chunk series: blocks of >= kMinBlockRows rows
+    // (NZ / bz + 8 blocks at most, z groups cut blocks), per column
+    const int bzmin = o.harm_block ? o.harm_block : kMinBlockRows;
+    p->pyr_cap = chunk * (int64_t)(g.NZ / bzmin + 9) * pitch;
+    if ((s = dalloc(p, &p->d_pyr, p->pyr_cap, "block maxima")) != FDAS_OK) return bail(s);
     const int NS = nstages_of(numharm);
     p->maxv_cap = chunk * NS * round_up(max_nsamp, 16);
     if ((s = dalloc(p, &p->d_maxv, p->maxv_cap, "stage maxima")) != FDAS_OK) return bail(s);
@@ -579,7 +911,7 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     if ((s = dalloc(p, &p->d_rec, p->rec_cap, "candidate records")) != FDAS_OK) return bail(s);
     if ((s = halloc(p, &p->h_state, 2, "state")) != FDAS_OK) return bail(s);
     if ((s = halloc(p, &p->h_small, 8, "thresholds")) != FDAS_OK) return bail(s);
-    if ((s = halloc(p, &p->h_scale, max_series, "scales")) != FDAS_OK) return bail(s);
+    if ((s = halloc(p, &p->h_offs, max_series, "series offsets")) != FDAS_OK) return bail(s);
     p->h_rec_cap = 4096;
     if ((s = halloc(p, &p->h_rec, p->h_rec_cap, "candidate staging")) != FDAS_OK) return bail(s);
     *out = p;
@@ -591,45 +923,85 @@ fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int
                         fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream) {
     Geometry g;
     TRY(check_common(p, series_dev, nsamp, nseries, tsamp, zmax, dz, g));
-    if (!valid_numharm(numharm) || numharm > p->max_numharm)
-        return p->fail(FDAS_E_INVAL, "numharm must be a power of two up to the plan's numharm");
-    if (!(sigma > 0) || !std::isfinite(sigma)) return p->fail(FDAS_E_INVAL, "sigma must be finite and > 0");
-    if (cap < 0 || (cap > 0 && !out_host) || !n_total) return p->fail(FDAS_E_INVAL, "bad output buffer");
-    TRY(ensure_bank(p, zmax, dz));
+    TRY(check_search(p, numharm, sigma, out_host, cap, n_total));
+    TRY(check_fits(p, g));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const CorrGeom cg = corr_geom(p, g);
-    const int64_t pitch = round_up(g.NR, 64);
-    const int64_t sstride = (int64_t)g.NZ * pitch;
-    if (sstride > p->plane_cap)
-        return p->fail(FDAS_E_INVAL, "one series' plane exceeds the workspace; create the plan with this zmax");
-    const int chunk = (int)std::min<int64_t>(p->chunk_series, p->plane_cap / sstride);
-    // bounded harmonic sums need the block maxima of every chunk series
-    // (K4 always writes them, so both harmonic-sum modes read the same plane)
-    RowBlocks rb;
-    TRY(ensure_row_blocks(p, g.NZ, cg.zgroups, block_rows(p, numharm), numharm, rb));
-    const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? pitch / 2 : pitch);
-    float *pyr = (psstride * chunk <= p->pyr_cap) ? p->d_pyr : nullptr;
-    const float *pyr_k5 = (p->opts.harm_bound || bounded_lds_bytes(rb.nblk, numharm) > kBoundLdsMax)
-                              ? nullptr : pyr;
-    p->last_harm_blocks = pyr_k5 ? rb.nblk : 0;
-    p->last_harm_pair = rb.pair ? 1 : 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        TRY(run_spectrum(p, series_dev, g, nseries, st));
-        TRY(prepare_harm(p, g, numharm, sigma, st));
-        for (int b0 = 0; b0 < nseries; b0 += chunk) {
-            const int nb = std::min(chunk, nseries - b0);
-            hipEvent_t e = p->begin(st);
-            HIPTRY(p, launch_corr_power(p->d_spec + (int64_t)b0 * p->spitch, p->spitch, p->d_scale + b0,
-                                        p->d_bank, cg, nb, p->d_plane, pitch, sstride, pyr, psstride, rb, st));
-            p->end(2, e, st);
-            TRY(run_harm_chunk(p, p->d_plane, pitch, sstride, g, numharm, b0, nb, st, pyr_k5, psstride, &rb));
+    Batch B;
+    B.groups.resize(1);
+    Group &G = B.groups[0];
+    G.g = g;
+    G.zmax = g.Z * dz;
+    G.nb = nseries;
+    G.vbase = 0;
+    B.vmap.resize(nseries);
+    for (int i = 0; i < nseries; ++i) B.vmap[i] = i;
+    B.vgroup.assign(nseries, 0);
+    B.vT.assign(nseries, g.T);
+    TRY(upload_thresholds(p, numharm, sigma, st));
+    TRY(group_cfg(p, g, G.zmax, dz, numharm, series_dev, nullptr, nseries, st, &G.cfg));
+    std::ostringstream key;
+    key << "h " << (const void *)series_dev << ' ' << dz << ' ' << numharm << ' ' << p->rec_cap;
+    key_group(key, G);
+    return run_batch(p, series_dev, false, B, dz, numharm, key.str(), out_host, cap, n_total, st);
+}
+
+fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64_t *offsets,
+                               const int64_t *nsamp, const double *tsamp, const double *zmax,
+                               int32_t nseries, double dz, int32_t numharm, double sigma,
+                               fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream) {
+    TRY(check_plan(p));
+    if (!series_dev || ((uintptr_t)series_dev & 7) || !offsets || !nsamp || !tsamp || !zmax)
+        return p->fail(FDAS_E_INVAL, "NULL or misaligned argument");
+    if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
+    TRY(check_search(p, numharm, sigma, out_host, cap, n_total));
+    // group series by (nsamp, band, zmax), groups in order of first appearance
+    std::map<std::tuple<int64_t, int64_t, int>, int> gid;
+    Batch B;
+    std::vector<std::vector<int>> members;
+    std::vector<Geometry> geo(nseries);
+    for (int i = 0; i < nseries; ++i) {
+        Geometry &g = geo[i];
+        if (offsets[i] < 0 || (offsets[i] & 1)) return p->fail(FDAS_E_INVAL, "series offset negative or odd");
+        if (nsamp[i] > p->max_nsamp) return p->fail(FDAS_E_INVAL, "nsamp exceeds the plan's max_nsamp");
+        fdas_status s = geometry(nsamp[i], tsamp[i], zmax[i], dz, p->opts.flo_hz, g);
+        if (s != FDAS_OK) return p->fail(s, "invalid nsamp/tsamp/zmax/dz of a series");
+        if (!pow2(nsamp[i])) return p->fail(FDAS_E_UNSUPPORTED, "nsamp must be a power of two");
+        TRY(check_fits(p, g));
+        const auto key = std::make_tuple(g.nsamp, g.rlo, g.Z);
+        auto it = gid.find(key);
+        if (it == gid.end()) {
+            it = gid.emplace(key, (int)B.groups.size()).first;
+            Group G;
+            G.g = g;
+            G.zmax = g.Z * dz;
+            B.groups.push_back(G);
+            members.emplace_back();
         }
-        bool regrow = false;
-        fdas_status s = finish(p, g, numharm, dz, out_host, cap, n_total, st, &regrow);
-        if (!regrow) return s;
-        TRY(grow_records(p, std::min<int64_t>(p->h_state[0], cap)));
+        members[it->second].push_back(i);
     }
-    return p->fail(FDAS_E_DEVICE, "internal error: candidate capacity did not converge");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (size_t gi = 0; gi < B.groups.size(); ++gi) {
+        Group &G = B.groups[gi];
+        G.vbase = (int)B.vmap.size();
+        G.nb = (int)members[gi].size();
+        for (int i : members[gi]) {
+            p->h_offs[B.vmap.size()] = offsets[i] / 2;   // complex-sample units
+            B.vmap.push_back(i);
+            B.vgroup.push_back((int)gi);
+            B.vT.push_back(geo[i].T);
+        }
+    }
+    TRY(upload_thresholds(p, numharm, sigma, st));
+    HIPTRY(p, hipMemcpyAsync(p->d_offs, p->h_offs, nseries * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    for (auto &G : B.groups)
+        TRY(group_cfg(p, G.g, G.zmax, dz, numharm, series_dev, p->d_offs + G.vbase, G.nb, st, &G.cfg));
+    // graph key: every value the enqueued launches depend on (offsets are
+    // read from device memory, uploaded every call)
+    std::ostringstream key;
+    key << "r " << (const void *)series_dev << ' ' << nseries << ' ' << dz << ' ' << numharm << ' '
+        << p->rec_cap;
+    for (const auto &G : B.groups) key_group(key, G);
+    return run_batch(p, series_dev, true, B, dz, numharm, key.str(), out_host, cap, n_total, st);
 }
 
 fdas_status fdas_plane(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
@@ -639,12 +1011,15 @@ fdas_status fdas_plane(fdas_plan p, const float *series_dev, int64_t nsamp, int3
     TRY(check_common(p, series_dev, nsamp, nseries, tsamp, zmax, dz, g));
     if (!plane_dev || ((uintptr_t)plane_dev & 7) || plane_elems < (int64_t)nseries * g.NZ * g.NR)
         return p->fail(FDAS_E_INVAL, "plane buffer NULL, misaligned or too small");
-    TRY(ensure_bank(p, zmax, dz));
+    const LaunchCfg c = default_cfg(p, g.Z, dz, 1);
+    if (!c.L) return p->fail(FDAS_E_UNSUPPORTED, "zmax too large for the supported segment lengths");
+    const Bank *bk = nullptr;
+    TRY(get_bank(p, g.Z * dz, dz, c.L, &bk));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    TRY(run_spectrum(p, series_dev, g, nseries, st));
-    const CorrGeom cg = corr_geom(p, g);
+    TRY(run_spectrum(p, series_dev, nullptr, g, nseries, st));
+    const CorrGeom cg = corr_geom(*bk, g);
     hipEvent_t e = p->begin(st);
-    HIPTRY(p, launch_corr_power(p->d_spec, p->spitch, p->d_scale, p->d_bank, cg, nseries, plane_dev, g.NR,
+    HIPTRY(p, launch_corr_power(p->d_spec, p->spitch, p->d_scale, bk->d, cg, nseries, plane_dev, g.NR,
                                 (int64_t)g.NZ * g.NR, nullptr, 0, RowBlocks(), st));
     p->end(2, e, st);
     HIPTRY(p, hipStreamSynchronize(st));
@@ -657,52 +1032,68 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
                          fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream) {
     Geometry g;
     TRY(check_common(p, plane_dev, nsamp, nseries, tsamp, zmax, dz, g));
-    if (!valid_numharm(numharm) || numharm > p->max_numharm)
-        return p->fail(FDAS_E_INVAL, "numharm must be a power of two up to the plan's numharm");
-    if (!(sigma > 0) || !std::isfinite(sigma)) return p->fail(FDAS_E_INVAL, "sigma must be finite and > 0");
-    if (cap < 0 || (cap > 0 && !out_host) || !n_total) return p->fail(FDAS_E_INVAL, "bad output buffer");
+    TRY(check_search(p, numharm, sigma, out_host, cap, n_total));
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t sstride = (int64_t)g.NZ * g.NR;
     const int NS = nstages_of(numharm);
-    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(p->max_series,
-                                                 p->maxv_cap / (NS * round_up(g.NR, 16))));
+    const int64_t mpitch = round_up(g.NR, 16);
     // block maxima of the caller's plane for the bounded sums (row blocks as a
     // single z group; results do not depend on the partition)
     RowBlocks rb;
-    int64_t psstride = 0;
-    int pchunk = chunk;
-    if (!p->opts.harm_bound) {
-        TRY(ensure_row_blocks(p, g.NZ, 1, block_rows(p, numharm), numharm, rb));
-        psstride = (int64_t)rb.nblk * (rb.pair ? g.NR / 2 : g.NR);
-        pchunk = (int)std::min<int64_t>(chunk, p->pyr_cap / std::max<int64_t>(1, psstride));
-    }
-    const bool bounded = !p->opts.harm_bound && pchunk >= 1 &&
-                         bounded_lds_bytes(rb.nblk, numharm) <= kBoundLdsMax;
-    const int step = bounded ? pchunk : chunk;
+    TRY(get_rows(p, g.NZ, 1, p->opts.harm_block ? p->opts.harm_block : default_block_rows(numharm), numharm,
+                 p->opts.harm_pair == 0, rb));
+    const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? g.NR / 2 : g.NR);
+    int64_t chunk = std::min<int64_t>(p->max_series, p->maxv_cap / (NS * mpitch));
+    const bool bounded = !p->opts.harm_bound && bounded_lds_bytes(rb.nblk, numharm) <= kBoundLdsMax &&
+                         p->pyr_cap >= psstride;
+    if (bounded) chunk = std::min<int64_t>(chunk, p->pyr_cap / psstride);
+    if (chunk < 1) return p->fail(FDAS_E_INVAL, "one series exceeds the workspace");
+    Batch B;
+    B.groups.resize(1);
+    B.groups[0].g = g;
+    B.vmap.resize(nseries);
+    for (int i = 0; i < nseries; ++i) B.vmap[i] = i;
+    B.vgroup.assign(nseries, 0);
+    B.vT.assign(nseries, g.T);
     for (int attempt = 0; attempt < 2; ++attempt) {
-        TRY(prepare_harm(p, g, numharm, sigma, st));
-        for (int b0 = 0; b0 < nseries; b0 += step) {
-            const int nb = std::min(step, nseries - b0);
+        TRY(upload_thresholds(p, numharm, sigma, st));
+        HIPTRY(p, launch_zero_state(p->d_state, st));
+        for (int b0 = 0; b0 < nseries; b0 += (int)chunk) {
+            const int nb = (int)std::min<int64_t>(chunk, nseries - b0);
             const float *pl = plane_dev + (int64_t)b0 * sstride;
+            hipEvent_t e = p->begin(st);
             if (bounded) {
                 HIPTRY(p, launch_block_max(pl, g.NR, sstride, g.NR, rb, nb, p->d_pyr, psstride, st));
-                TRY(run_harm_chunk(p, pl, g.NR, sstride, g, numharm, b0, nb, st, p->d_pyr, psstride, &rb));
+                HIPTRY(p, launch_harmsum_bounded(pl, g.NR, sstride, p->d_pyr, psstride, rb, g.NR, g.rlo, g.Z,
+                                                 numharm, nb, p->d_thr, p->d_maxv, mpitch, st));
             } else {
-                TRY(run_harm_chunk(p, pl, g.NR, sstride, g, numharm, b0, nb, st));
+                const int order = p->opts.harm_order ? p->opts.harm_order : 1;
+                HIPTRY(p, launch_harmsum(pl, g.NR, sstride, g.NR, g.rlo, g.Z, numharm, nb, p->d_maxv, mpitch,
+                                         order, st));
             }
+            p->end(3, e, st);
+            e = p->begin(st);
+            HIPTRY(p, launch_compact(p->d_maxv, (int64_t)nb * NS * mpitch, mpitch, NS, b0, p->d_thr, p->d_counts,
+                                     p->d_offsets, p->d_state, p->d_rec, p->rec_cap, st));
+            p->end(4, e, st);
+            e = p->begin(st);
+            HIPTRY(p, launch_argmax(pl, g.NR, sstride, g.rlo, g.Z, numharm, b0, p->d_rec, p->d_state, p->rec_cap,
+                                    st));
+            p->end(5, e, st);
         }
         bool regrow = false;
-        fdas_status s = finish(p, g, numharm, dz, out_host, cap, n_total, st, &regrow);
+        const fdas_status s = finish(p, B, dz, true, out_host, cap, n_total, st, &regrow);
         if (!regrow) return s;
-        TRY(grow_records(p, std::min<int64_t>(p->h_state[0], cap)));
+        TRY(dalloc(p, &p->d_rec, std::min<int64_t>(p->h_state[0], cap), "candidate records"));
+        p->rec_cap = std::min<int64_t>(p->h_state[0], cap);
+        drop_graph(p);
     }
     return p->fail(FDAS_E_DEVICE, "internal error: candidate capacity did not converge");
 }
 
 fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
                           float *spec_dev, double *norm_host, void *stream) {
-    if (!p) return FDAS_E_INVAL;
-    if (p->sticky) return p->fail(FDAS_E_DEVICE, "plan is in a failed state: " + p->last_error);
+    TRY(check_plan(p));
     if (!series_dev || ((uintptr_t)series_dev & 7) || !spec_dev || ((uintptr_t)spec_dev & 7))
         return p->fail(FDAS_E_INVAL, "device pointer NULL or not 8-byte aligned");
     if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
@@ -713,7 +1104,7 @@ fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, i
     g.nsamp = nsamp;
     g.half = nsamp / 2;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    TRY(run_spectrum(p, series_dev, g, nseries, st));
+    TRY(run_spectrum(p, series_dev, nullptr, g, nseries, st));
     HIPTRY(p, hipMemcpy2DAsync(spec_dev, (size_t)(g.half + 1) * sizeof(float2), p->d_spec,
                                (size_t)p->spitch * sizeof(float2), (size_t)(g.half + 1) * sizeof(float2),
                                (size_t)nseries, hipMemcpyDeviceToDevice, st));
@@ -731,13 +1122,57 @@ fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, i
 
 fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out) {
     if (!p || !out) return FDAS_E_INVAL;
-    out->seg_len = p->L;
-    out->mseg = p->mseg;
-    out->nz = p->bankNZ;
-    out->chunk_series = p->chunk_series;
+    const Bank *first = p->banks.empty() ? nullptr : &p->banks.front();
+    out->seg_len = p->last_L ? p->last_L : (first ? first->L : 0);
+    out->mseg = p->last_L ? p->last_mseg : (first ? first->mseg : 0);
+    out->nz = p->last_L ? p->last_NZ : (first ? first->NZ : 0);
+    const int64_t per = (first ? first->NZ : 1) * round_up(p->max_nsamp, 64);
+    out->chunk_series = (int32_t)std::min<int64_t>(p->max_series, p->plane_cap / per);
     out->workspace_bytes = p->plane_cap * (int64_t)sizeof(float);
     out->harm_blocks = p->last_harm_blocks;
     out->harm_pair = p->last_harm_pair;
+    return FDAS_OK;
+}
+
+fdas_status fdas_tuning_export(fdas_plan p, char *buf, int64_t cap, int64_t *len) {
+    if (!p || !len || cap < 0 || (cap > 0 && !buf)) return FDAS_E_INVAL;
+    std::ostringstream os;
+    for (auto &kv : p->tuned)
+        os << std::get<0>(kv.first) << ' ' << std::get<1>(kv.first) << ' ' << std::get<2>(kv.first) << ' '
+           << kv.second.L << ' ' << kv.second.bz << ' ' << (kv.second.pair ? 0 : 1) << '\n';
+    const std::string s = os.str();
+    *len = (int64_t)s.size();
+    if (cap > 0) {
+        const int64_t n = std::min<int64_t>(cap - 1, (int64_t)s.size());
+        std::memcpy(buf, s.data(), (size_t)n);
+        buf[n] = 0;
+    }
+    return (cap == 0 || cap > (int64_t)s.size()) ? FDAS_OK : FDAS_E_TRUNC;
+}
+
+fdas_status fdas_tuning_import(fdas_plan p, const char *text) {
+    if (!p || !text) return FDAS_E_INVAL;
+    std::istringstream is(text);
+    std::string line;
+    std::vector<std::pair<std::tuple<int64_t, int, int>, LaunchCfg>> add;
+    while (std::getline(is, line)) {
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        std::istringstream ls(line);
+        int64_t n = 0;
+        int Z = -1, nh = 0, L = 0, bz = 0, harm_pair = -1;
+        std::string rest;
+        if (!(ls >> n >> Z >> nh >> L >> bz >> harm_pair) || (ls >> rest) || !pow2(n) || Z < 0 ||
+            !valid_numharm(nh) || !pow2(L) || L < 512 || L > 4096 || bz < 1 || bz > 64 ||
+            (harm_pair != 0 && harm_pair != 1))
+            return p->fail(FDAS_E_INVAL, "malformed tuning line: " + line);
+        LaunchCfg c;
+        c.L = L;
+        c.bz = bz;
+        c.pair = harm_pair ? 0 : 1;
+        add.emplace_back(std::make_tuple(n, Z, nh), c);
+    }
+    for (auto &kv : add) p->tuned[kv.first] = kv.second;
+    drop_graph(p);
     return FDAS_OK;
 }
 

@@ -42,13 +42,20 @@ struct DevCand {
 // K1: real FFT of nseries series of n samples (n a power of two >= 8).
 // x: [nseries][n] float32; w0, w1: scratch [nseries][n/2] complex; spec: [nseries][spitch]
 // complex receiving A_k for k = 0..n/2.
+// offs (device, optional): series b starts at x + 2 offs[b] floats (ragged batches);
+// otherwise series b starts at x + b n.
 hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float2 *w1,
-                       float2 *spec, int64_t spitch, hipStream_t st);
+                       float2 *spec, int64_t spitch, hipStream_t st, const int64_t *offs = nullptr);
+
+// state[0] = state[1] = 0 (a kernel, so that captured graphs hold no memset node).
+hipError_t launch_zero_state(int64_t *state, hipStream_t st);
 
 // K2: lower median of |A_k|^2 (k = 1..n/2-1) per series -> norm (FP64) and the
 // amplitude scale sqrt(1/norm) (0 when the median is 0).
 hipError_t launch_median_scale(const float2 *spec, int64_t spitch, int64_t half, int nseries,
                                float *scale, double *norm, hipStream_t st);
+// scale[0..nseries) = value (the fixed-variance normalisation).
+hipError_t launch_fill_scale(float *scale, int nseries, float value, hipStream_t st);
 
 // K4: overlap-save correlation with the template bank and power.
 struct CorrGeom {

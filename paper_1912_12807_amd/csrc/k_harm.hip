@@ -564,6 +564,15 @@ hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t ser
     return hipGetLastError();
 }
 
+__global__ void k_zero_state(int64_t *state) {
+    if (threadIdx.x < 2) state[threadIdx.x] = 0;
+}
+
+hipError_t launch_zero_state(int64_t *state, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, st, state);
+    return hipGetLastError();
+}
+
 int64_t compact_blocks(int64_t nelem) { return (nelem + kCB - 1) / kCB; }
 
 hipError_t launch_compact(const float *maxv, int64_t nelem, int64_t mpitch, int nstages, int b0,

@@ -89,4 +89,15 @@ hipError_t launch_median_scale(const float2 *spec, int64_t spitch, int64_t half,
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_fill_scale(float *__restrict__ scale, int n, float v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) scale[i] = v;
+}
+
+hipError_t launch_fill_scale(float *scale, int nseries, float value, hipStream_t st) {
+    if (nseries < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_scale, dim3((nseries + 255) / 256), dim3(256), 0, st, scale, nseries, value);
+    return hipGetLastError();
+}
+
 }  // namespace fdas

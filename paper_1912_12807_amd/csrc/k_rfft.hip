@@ -16,14 +16,16 @@ namespace fdas {
 
 // One Stockham pass: butterfly j reads in[j + r M/R], writes out[(j - k) R + k + r Ns],
 // k = j mod Ns, after twiddling input r by exp(DIR 2 pi i k r / (Ns R)).
+// offs (optional, first pass only): series b starts at in + offs[b] complex values.
 template <int R, int DIR>
 __global__ __launch_bounds__(256) void k_stockham_pass(const float2 *__restrict__ in,
                                                        float2 *__restrict__ out, int64_t M,
-                                                       int64_t Ns, int64_t pin, int64_t pout) {
+                                                       int64_t Ns, int64_t pin, int64_t pout,
+                                                       const int64_t *__restrict__ offs) {
     const int64_t nb = M / R;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nb) return;
-    const float2 *src = in + (int64_t)blockIdx.y * pin;
+    const float2 *src = in + (offs ? offs[blockIdx.y] : (int64_t)blockIdx.y * pin);
     float2 *dst = out + (int64_t)blockIdx.y * pout;
     float2 v[R];
 #pragma unroll
@@ -55,14 +57,14 @@ __global__ __launch_bounds__(256) void k_rfft_post(const float2 *__restrict__ Z,
 
 template <int R>
 static void pass(const float2 *in, float2 *out, int64_t M, int64_t Ns, int64_t pin, int64_t pout,
-                 int nseries, hipStream_t st) {
+                 int nseries, const int64_t *offs, hipStream_t st) {
     const int64_t nb = M / R;
     dim3 grid((unsigned)((nb + 255) / 256), (unsigned)nseries);
-    hipLaunchKernelGGL((k_stockham_pass<R, -1>), grid, dim3(256), 0, st, in, out, M, Ns, pin, pout);
+    hipLaunchKernelGGL((k_stockham_pass<R, -1>), grid, dim3(256), 0, st, in, out, M, Ns, pin, pout, offs);
 }
 
 hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float2 *w1,
-                       float2 *spec, int64_t spitch, hipStream_t st) {
+                       float2 *spec, int64_t spitch, hipStream_t st, const int64_t *offs) {
     const int64_t M = n / 2;
     if (M < 4 || (M & (M - 1)) || nseries < 1 || nseries > 65535) return hipErrorInvalidValue;
     int p = 0;
@@ -75,15 +77,17 @@ hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float
     int64_t Ns = 1;
     int rem = p % 3;
     if (rem) {
-        if (rem == 1) pass<2>(src, bufs[which], M, Ns, pin, M, nseries, st);
-        else pass<4>(src, bufs[which], M, Ns, pin, M, nseries, st);
+        if (rem == 1) pass<2>(src, bufs[which], M, Ns, pin, M, nseries, offs, st);
+        else pass<4>(src, bufs[which], M, Ns, pin, M, nseries, offs, st);
+        offs = nullptr;
         Ns *= (rem == 1) ? 2 : 4;
         src = bufs[which];
         which ^= 1;
         pin = M;
     }
     while (Ns < M) {
-        pass<8>(src, bufs[which], M, Ns, pin, M, nseries, st);
+        pass<8>(src, bufs[which], M, Ns, pin, M, nseries, offs, st);
+        offs = nullptr;
         Ns *= 8;
         src = bufs[which];
         which ^= 1;

@@ -16,20 +16,32 @@ namespace fdas {
 
 static constexpr double kPi = 3.14159265358979323846264338327950288;
 
+// log j! for the harmonic counts of a search (the same std::lgamma values,
+// computed once).
+static double log_factorial(int j) {
+    static const struct Table {
+        double v[65];
+        Table() {
+            for (int i = 0; i < 65; ++i) v[i] = std::lgamma(i + 1.0);
+        }
+    } t;
+    return j < 65 ? t.v[j] : std::lgamma(j + 1.0);
+}
+
 // log Q(H, S) by a log-sum-exp over the H terms of the finite series.
 double log_gamma_sf(int H, double S) {
     if (S <= 0.0) return 0.0;
     double ls = std::log(S);
     double mx = -INFINITY;
-    for (int j = 0; j < H; ++j) mx = std::fmax(mx, j * ls - std::lgamma(j + 1.0));
+    for (int j = 0; j < H; ++j) mx = std::fmax(mx, j * ls - log_factorial(j));
     double acc = 0.0;
-    for (int j = 0; j < H; ++j) acc += std::exp(j * ls - std::lgamma(j + 1.0) - mx);
+    for (int j = 0; j < H; ++j) acc += std::exp(j * ls - log_factorial(j) - mx);
     return -S + mx + std::log(acc);
 }
 
 // d/dS log Q(H, S) = -(S^(H-1)/(H-1)!) exp(-S) / Q(H, S).
 static double dlog_gamma_sf(int H, double S, double logq) {
-    return -std::exp((H - 1) * std::log(S) - std::lgamma((double)H) - S - logq);
+    return -std::exp((H - 1) * std::log(S) - log_factorial(H - 1) - S - logq);
 }
 
 // log of the Gaussian upper tail, log(erfc(s / sqrt 2) / 2), for any s.

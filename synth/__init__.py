@@ -160,6 +160,93 @@ def config3(nseries: int = 32, nsamp: int = 1 << 23) -> Workload:
     return Workload("pmps-long-32x2^23", 3, nsamp, nseries, tsamp, 200.0, 2.0, 16, 6.0, inj)
 
 
+@dataclasses.dataclass
+class RaggedWorkload:
+    """A batch whose series differ in length, sampling time and searched drift."""
+    name: str
+    config: int
+    nsamp: List[int]
+    tsamp: List[float]
+    zmax: List[float]
+    dz: float
+    numharm: int
+    sigma: float
+    injections: List[Injection]
+    noise: bool = True
+
+    @property
+    def nseries(self) -> int:
+        return len(self.nsamp)
+
+    def offsets(self, series_idx=None) -> np.ndarray:
+        """Start of each selected series in the packed buffer (elements)."""
+        idx = range(self.nseries) if series_idx is None else series_idx
+        n = np.array([self.nsamp[i] for i in idx], dtype=np.int64)
+        return np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+
+
+def config4(nseries: int = 512, tobs: float = 52.4288, noise: bool = True) -> RaggedWorkload:
+    """Uneven batch: 512 series of 2^16..2^20 samples (exponent uniform, so lengths are
+    log-uniform) covering the same 52.4288 s, as dedispersion trials downsampled by
+    different factors are; zmax per series from {0, 50, 100, 200, 300}; 10 % of the
+    series carry a pulse train with |z| <= 0.75 zmax."""
+    rng = np.random.Generator(np.random.PCG64(seed_for(4, 999)))
+    expo = rng.integers(16, 21, nseries)
+    nsamp = [int(1 << int(e)) for e in expo]
+    tsamp = [tobs / n for n in nsamp]
+    zchoices = np.array([0.0, 50.0, 100.0, 200.0, 300.0])
+    zmax = [float(z) for z in zchoices[rng.integers(0, 5, nseries)]]
+    carriers = sorted(rng.choice(nseries, size=max(1, nseries // 10), replace=False).tolist())
+    inj = []
+    for b in carriers:
+        ts = tsamp[b]
+        period = math.exp(rng.uniform(math.log(max(8 * ts, 1e-3)), math.log(0.5)))
+        inj.append(Injection(series=int(b), kind="pulse", r0=tobs / period,
+                             z0=rng.uniform(-0.75, 0.75) * zmax[b],
+                             amp=math.exp(rng.uniform(math.log(0.05), math.log(0.5))),
+                             duty=rng.uniform(0.02, 0.10), phase0=rng.uniform(0.0, 1.0)))
+    return RaggedWorkload(f"uneven-{nseries}x2^16..2^20", 4, nsamp, tsamp, zmax, 2.0, 8, 6.0, inj,
+                          noise=noise)
+
+
+def small_ragged(nsamp, tsamp, zmax, dz: float = 2.0, numharm: int = 4, sigma: float = 6.0,
+                 config: int = 98, signals: int = 3, amp_range=(0.2, 0.8)) -> RaggedWorkload:
+    """A small seeded ragged batch for parity tests (pulse trains in a few series)."""
+    rng = np.random.Generator(np.random.PCG64(seed_for(config, 777)))
+    nser = len(nsamp)
+    inj = []
+    for b in sorted(rng.choice(nser, size=min(signals, nser), replace=False).tolist()):
+        tobs = nsamp[b] * tsamp[b]
+        period = math.exp(rng.uniform(math.log(max(8 * tsamp[b], 2e-3)), math.log(tobs / 40.0)))
+        inj.append(Injection(series=int(b), kind="pulse", r0=tobs / period,
+                             z0=rng.uniform(-0.75, 0.75) * zmax[b],
+                             amp=math.exp(rng.uniform(math.log(amp_range[0]), math.log(amp_range[1]))),
+                             duty=rng.uniform(0.02, 0.10), phase0=rng.uniform(0, 1)))
+    return RaggedWorkload(f"ragged-{nser}", config, [int(n) for n in nsamp], [float(t) for t in tsamp],
+                          [float(z) for z in zmax], dz, numharm, sigma, inj)
+
+
+def generate_series(wl, b: int) -> np.ndarray:
+    """Series b of a ragged workload as float32 [nsamp[b]]."""
+    x = _series(wl.nsamp[b], seed_for(wl.config, b), wl.noise)
+    for inj in wl.injections:
+        if inj.series == b:
+            add_pulse(x, inj.r0, inj.z0, inj.amp, inj.duty, inj.phase0)
+    return x.astype(np.float32)
+
+
+def generate_ragged(wl: RaggedWorkload, series_idx=None) -> np.ndarray:
+    """The selected series packed back to back (float32), in the order given;
+    their starts are wl.offsets(series_idx)."""
+    idx = list(range(wl.nseries)) if series_idx is None else list(series_idx)
+    out = np.empty(sum(wl.nsamp[i] for i in idx), dtype=np.float32)
+    pos = 0
+    for i in idx:
+        out[pos:pos + wl.nsamp[i]] = generate_series(wl, i)
+        pos += wl.nsamp[i]
+    return out
+
+
 def generate(wl: Workload, series_idx=None) -> np.ndarray:
     """float32 [len(series_idx)][nsamp]; default: the whole batch."""
     if series_idx is None:
