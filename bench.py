@@ -50,14 +50,17 @@ def kernel_hash(phase: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(phase: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if still current."""
+def measured_traffic(phase: str, workload: str, seg_len: int = None):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if still current
+    (same kernel source and, for the plane, the same segment length)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh).get(f"{workload}:{phase}")
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_hash") != kernel_hash(phase):
+        return None
+    if phase == "plane" and rec.get("seg_len") != seg_len:
         return None
     return rec.get("bytes_per_launch")
 
@@ -190,7 +193,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, workload: str, command: str):
     return res, "\n".join(lines) + "\n", f_scale, w_scale
 
 
-def write_traffic(res, workload, f_scale, w_scale):
+def write_traffic(res, workload, f_scale, w_scale, seg_len=None):
     """profiles/traffic.json entries for the dominant-kernel candidates, keyed by source hash."""
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -205,7 +208,8 @@ def write_traffic(res, workload, f_scale, w_scale):
                                            "fetch_bytes": hits[0]["fetch_bytes"],
                                            "write_bytes": hits[0]["write_bytes"],
                                            "fetch_scale": f_scale, "write_scale": w_scale,
-                                           "kernel_hash": kernel_hash(phase)}
+                                           "kernel_hash": kernel_hash(phase),
+                                           **({"seg_len": seg_len} if phase == "plane" else {})}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
 
@@ -218,12 +222,16 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
+                    help="time candidate launch parameters on the first search (during warmup)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("STATS_CSV", "OUT_MD", "COMMAND"),
                     help="write a markdown summary of a rocprofv3 kernel-stats CSV and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND"),
                     help="summarise FETCH_SIZE/WRITE_SIZE runs into OUT_MD and profiles/traffic.json")
+    ap.add_argument("--pmc-seg-len", type=int, default=2048,
+                    help="segment length the counter runs used (recorded with the plane traffic)")
     args = ap.parse_args()
     if args.stats_summary:
         csv_path, out_md, cmd = args.stats_summary
@@ -237,7 +245,7 @@ def main():
         res, md, fs, ws = pmc_summary(fcsv, wcsv, wl.name, cmd)
         with open(out_md, "w") as fh:
             fh.write(md)
-        write_traffic(res, wl.name, fs, ws)
+        write_traffic(res, wl.name, fs, ws, args.pmc_seg_len)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -263,7 +271,7 @@ def main():
     x = torch.from_numpy(synth.generate(wl)).cuda()
     rlo, nr, nz = fdas.geometry(wl.nsamp, wl.tsamp, wl.zmax, wl.dz)
     cells = wl.nseries * nr * nz
-    plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1)
+    plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1, autotune=args.autotune)
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -285,6 +293,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = plan.profile(reset=True)
+    tuning = plan.tuning().strip()
     ms_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall
 
@@ -325,7 +334,7 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "kernel": DOMINANT[dom] if info["harm_blocks"] else "k_harmsum",
                 "per_unit": f"{byts / cells_launch:.3f} B/cell"}
-    roof["traffic"] = measured_traffic(dom, wl.name)
+    roof["traffic"] = measured_traffic(dom, wl.name, L)
     roof["launch_ms"] = t_launch * 1e3
 
     plain = None
@@ -356,7 +365,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "nseries": wl.nseries, "nsamp": wl.nsamp, "tsamp": wl.tsamp,
                    "zmax": wl.zmax, "dz": wl.dz, "numharm": wl.numharm, "sigma": wl.sigma,
-                   "cells_per_step": cells, "seg_len": L, "parallelism": "single GPU"},
+                   "cells_per_step": cells, "seg_len": L, "harm_block_rows": tuning.split()[4] if tuning else None,
+                   "tuning": tuning or None, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_path": plain,

@@ -138,6 +138,7 @@ struct fdas_plan_s {
     float2 *d_spec = nullptr, *d_w0 = nullptr, *d_w1 = nullptr;
     float *d_scale = nullptr;
     double *d_norm = nullptr;
+    uint8_t *d_med = nullptr;   // median-select scratch
     float *d_thr = nullptr;
     int64_t *d_state = nullptr;
     int64_t *d_offs = nullptr;  // ragged series offsets (complex units), group order
@@ -403,25 +404,29 @@ CorrGeom corr_geom(const Bank &bk, const Geometry &g) {
 
 // ---------------------------------------------------------------- enqueue helpers
 
-// K1 + K2 for nb series (series b at x + b nsamp, or at x + 2 offs[b] floats).
-fdas_status run_spectrum(fdas_plan p, const float *x, const int64_t *offs, const Geometry &g, int nb,
+// K1 + K2 for nb series of nsamp samples (series b at x + b nsamp, or at
+// x + 2 offs[b] floats); spectra, scales and norms go to batch slots v0...
+fdas_status run_spectrum(fdas_plan p, const float *x, const int64_t *offs, int64_t nsamp, int nb, int v0,
                          hipStream_t st) {
+    float2 *spec = p->d_spec + (int64_t)v0 * p->spitch;
     hipEvent_t e = p->begin(st);
-    HIPTRY(p, launch_rfft(x, g.nsamp, nb, p->d_w0, p->d_w1, p->d_spec, p->spitch, st, offs));
+    HIPTRY(p, launch_rfft(x, nsamp, nb, p->d_w0, p->d_w1, spec, p->spitch, st, offs));
     p->end(0, e, st);
     if (p->opts.norm == FDAS_NORM_MEDIAN) {
         e = p->begin(st);
-        HIPTRY(p, launch_median_scale(p->d_spec, p->spitch, g.half, nb, p->d_scale, p->d_norm, st));
+        HIPTRY(p, launch_median_scale(spec, p->spitch, nsamp / 2, nb, p->d_scale + v0, p->d_norm + v0, p->d_med,
+                                      st));
         p->end(1, e, st);
     } else {
-        const float sc = (float)std::sqrt(1.0 / ((double)g.nsamp * p->opts.fixed_var));
-        HIPTRY(p, launch_fill_scale(p->d_scale, nb, sc, st));
+        const float sc = (float)std::sqrt(1.0 / ((double)nsamp * p->opts.fixed_var));
+        HIPTRY(p, launch_fill_scale(p->d_scale + v0, nb, sc, st));
     }
     return FDAS_OK;
 }
 
-// K4 [+ K5 + K6 + argmax] for the nb series whose spectra are in d_spec, in
-// chunks that the workspace holds. timing_only stops after K5 (autotuner).
+// K4 [+ K5 + K6 + argmax] for the nb series whose spectra are in batch slots
+// vbase..., in chunks that the workspace holds. timing_only stops after K5
+// (autotuner).
 fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const LaunchCfg &cfg,
                        int numharm, int nb, int vbase, bool timing_only, hipStream_t st) {
     const CorrGeom cg = corr_geom(bk, g);
@@ -444,8 +449,9 @@ fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
     for (int b0 = 0; b0 < nb; b0 += (int)chunk) {
         const int n = (int)std::min<int64_t>(chunk, nb - b0);
         hipEvent_t e = p->begin(st);
-        HIPTRY(p, launch_corr_power(p->d_spec + (int64_t)b0 * p->spitch, p->spitch, p->d_scale + b0, bk.d, cg,
-                                    n, p->d_plane, pitch, sstride, p->d_pyr, psstride, rb, st));
+        HIPTRY(p, launch_corr_power(p->d_spec + (int64_t)(vbase + b0) * p->spitch, p->spitch,
+                                    p->d_scale + vbase + b0, bk.d, cg, n, p->d_plane, pitch, sstride, p->d_pyr,
+                                    psstride, rb, st));
         p->end(2, e, st);
         e = p->begin(st);
         if (bounded) {
@@ -483,7 +489,7 @@ fdas_status upload_thresholds(fdas_plan p, int numharm, double sigma, hipStream_
 // shape, or (autotune) the fastest candidate timed on the group's first series
 // (K4 + K5 only; spectra of the sample are computed first).
 fdas_status group_cfg(fdas_plan p, const Geometry &g, double zmax, double dz, int numharm, const float *x,
-                      const int64_t *offs, int nb, hipStream_t st, LaunchCfg *out) {
+                      const int64_t *offs, int nb, int vbase, hipStream_t st, LaunchCfg *out) {
     const LaunchCfg base = default_cfg(p, g.Z, dz, numharm);
     if (!base.L) return p->fail(FDAS_E_UNSUPPORTED, "zmax too large for the supported segment lengths");
     *out = base;
@@ -505,16 +511,19 @@ fdas_status group_cfg(fdas_plan p, const Geometry &g, double zmax, double dz, in
     else if (numharm <= 8) bzs = {6, 8, 10, 12, 16};
     else if (numharm == 16) bzs = {4, 6, 8, 10};
     else bzs = {4, 6, 8};
-    const int sample = std::min<int>(nb, std::max<int64_t>(8, ((int64_t)1 << 21) / g.nsamp));
-    TRY(run_spectrum(p, x, offs, g, sample, st));
+    // time on enough series to fill the chip as the real launch does (about
+    // 2^31 plane cells), or on the whole group
+    const int64_t cells = (int64_t)g.NZ * g.NR;
+    const int sample = (int)std::min<int64_t>(nb, std::max<int64_t>(8, (((int64_t)1 << 31) + cells - 1) / cells));
+    TRY(run_spectrum(p, x, offs, g.nsamp, sample, vbase, st));
     hipEvent_t a = p->take_event(), b = p->take_event();
     if (!a || !b) return p->fail(FDAS_E_DEVICE, "event creation failed");
     auto time_cfg = [&](const LaunchCfg &c, float *ms) -> fdas_status {
         const Bank *bk = nullptr;
         TRY(get_bank(p, zmax, dz, c.L, &bk));
-        TRY(run_chunks(p, g, *bk, c, numharm, sample, 0, true, st));   // warm
+        TRY(run_chunks(p, g, *bk, c, numharm, sample, vbase, true, st));   // warm
         HIPTRY(p, hipEventRecord(a, st));
-        TRY(run_chunks(p, g, *bk, c, numharm, sample, 0, true, st));
+        TRY(run_chunks(p, g, *bk, c, numharm, sample, vbase, true, st));
         HIPTRY(p, hipEventRecord(b, st));
         HIPTRY(p, hipEventSynchronize(b));
         HIPTRY(p, hipEventElapsedTime(ms, a, b));
@@ -655,15 +664,23 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
     return total > cap ? FDAS_E_TRUNC : FDAS_OK;
 }
 
-// Enqueue every group of a batch on st.
+// Enqueue every group of a batch on st. Groups of one length are adjacent in
+// the batch, so each length needs one K1 and one K2 launch.
 fdas_status enqueue_groups(fdas_plan p, const float *x, bool ragged, const Batch &B, double dz, int numharm,
                            hipStream_t st) {
     HIPTRY(p, launch_zero_state(p->d_state, st));
-    for (const auto &G : B.groups) {
-        const Bank *bk = nullptr;
-        TRY(get_bank(p, G.zmax, dz, G.cfg.L, &bk));
-        TRY(run_spectrum(p, x, ragged ? p->d_offs + G.vbase : nullptr, G.g, G.nb, st));
-        TRY(run_chunks(p, G.g, *bk, G.cfg, numharm, G.nb, G.vbase, false, st));
+    for (size_t i = 0; i < B.groups.size();) {
+        size_t j = i;
+        int nb = 0;
+        while (j < B.groups.size() && B.groups[j].g.nsamp == B.groups[i].g.nsamp) nb += B.groups[j++].nb;
+        const int v0 = B.groups[i].vbase;
+        TRY(run_spectrum(p, x, ragged ? p->d_offs + v0 : nullptr, B.groups[i].g.nsamp, nb, v0, st));
+        for (; i < j; ++i) {
+            const Group &G = B.groups[i];
+            const Bank *bk = nullptr;
+            TRY(get_bank(p, G.zmax, dz, G.cfg.L, &bk));
+            TRY(run_chunks(p, G.g, *bk, G.cfg, numharm, G.nb, G.vbase, false, st));
+        }
     }
     return FDAS_OK;
 }
@@ -813,7 +830,7 @@ void fdas_plan_destroy(fdas_plan p) {
     if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
     for (auto &b : p->banks) (void)hipFree(b.d);
     for (auto &t : p->tables) (void)hipFree(t.d);
-    void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_thr, p->d_state, p->d_offs,
+    void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_med, p->d_thr, p->d_state, p->d_offs,
                    p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr};
     for (void *q : dev)
         if (q) (void)hipFree(q);
@@ -876,6 +893,8 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     if ((s = dalloc(p, &p->d_w1, (int64_t)max_series * half, "fft scratch")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_scale, max_series, "scales")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_norm, max_series, "norms")) != FDAS_OK) return bail(s);
+    if ((s = dalloc(p, &p->d_med, (int64_t)median_scratch_bytes(max_series), "median scratch")) != FDAS_OK)
+        return bail(s);
     if ((s = dalloc(p, &p->d_thr, 8, "thresholds")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_state, 2, "state")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_offs, max_series, "series offsets")) != FDAS_OK) return bail(s);
@@ -938,7 +957,7 @@ fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int
     B.vgroup.assign(nseries, 0);
     B.vT.assign(nseries, g.T);
     TRY(upload_thresholds(p, numharm, sigma, st));
-    TRY(group_cfg(p, g, G.zmax, dz, numharm, series_dev, nullptr, nseries, st, &G.cfg));
+    TRY(group_cfg(p, g, G.zmax, dz, numharm, series_dev, nullptr, nseries, 0, st, &G.cfg));
     std::ostringstream key;
     key << "h " << (const void *)series_dev << ' ' << dz << ' ' << numharm << ' ' << p->rec_cap;
     key_group(key, G);
@@ -954,7 +973,7 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
         return p->fail(FDAS_E_INVAL, "NULL or misaligned argument");
     if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
     TRY(check_search(p, numharm, sigma, out_host, cap, n_total));
-    // group series by (nsamp, band, zmax), groups in order of first appearance
+    // group series by (nsamp, band, zmax)
     std::map<std::tuple<int64_t, int64_t, int>, int> gid;
     Batch B;
     std::vector<std::vector<int>> members;
@@ -979,6 +998,18 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
         }
         members[it->second].push_back(i);
     }
+    // batch order: groups by (nsamp, band, zmax), so that groups of one length
+    // are adjacent; series in caller order inside a group
+    {
+        std::vector<Group> sorted;
+        std::vector<std::vector<int>> smembers;
+        for (const auto &kv : gid) {
+            sorted.push_back(B.groups[kv.second]);
+            smembers.push_back(std::move(members[kv.second]));
+        }
+        B.groups.swap(sorted);
+        members.swap(smembers);
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (size_t gi = 0; gi < B.groups.size(); ++gi) {
         Group &G = B.groups[gi];
@@ -994,7 +1025,7 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
     TRY(upload_thresholds(p, numharm, sigma, st));
     HIPTRY(p, hipMemcpyAsync(p->d_offs, p->h_offs, nseries * sizeof(int64_t), hipMemcpyHostToDevice, st));
     for (auto &G : B.groups)
-        TRY(group_cfg(p, G.g, G.zmax, dz, numharm, series_dev, p->d_offs + G.vbase, G.nb, st, &G.cfg));
+        TRY(group_cfg(p, G.g, G.zmax, dz, numharm, series_dev, p->d_offs + G.vbase, G.nb, G.vbase, st, &G.cfg));
     // graph key: every value the enqueued launches depend on (offsets are
     // read from device memory, uploaded every call)
     std::ostringstream key;
@@ -1016,7 +1047,7 @@ fdas_status fdas_plane(fdas_plan p, const float *series_dev, int64_t nsamp, int3
     const Bank *bk = nullptr;
     TRY(get_bank(p, g.Z * dz, dz, c.L, &bk));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    TRY(run_spectrum(p, series_dev, nullptr, g, nseries, st));
+    TRY(run_spectrum(p, series_dev, nullptr, g.nsamp, nseries, 0, st));
     const CorrGeom cg = corr_geom(*bk, g);
     hipEvent_t e = p->begin(st);
     HIPTRY(p, launch_corr_power(p->d_spec, p->spitch, p->d_scale, bk->d, cg, nseries, plane_dev, g.NR,
@@ -1104,7 +1135,7 @@ fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, i
     g.nsamp = nsamp;
     g.half = nsamp / 2;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    TRY(run_spectrum(p, series_dev, nullptr, g, nseries, st));
+    TRY(run_spectrum(p, series_dev, nullptr, g.nsamp, nseries, 0, st));
     HIPTRY(p, hipMemcpy2DAsync(spec_dev, (size_t)(g.half + 1) * sizeof(float2), p->d_spec,
                                (size_t)p->spitch * sizeof(float2), (size_t)(g.half + 1) * sizeof(float2),
                                (size_t)nseries, hipMemcpyDeviceToDevice, st));

@@ -51,9 +51,11 @@ hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float
 hipError_t launch_zero_state(int64_t *state, hipStream_t st);
 
 // K2: lower median of |A_k|^2 (k = 1..n/2-1) per series -> norm (FP64) and the
-// amplitude scale sqrt(1/norm) (0 when the median is 0).
+// amplitude scale sqrt(1/norm) (0 when the median is 0). scratch: device
+// memory of median_scratch_bytes(nseries) bytes (histograms and select state).
+size_t median_scratch_bytes(int nseries);
 hipError_t launch_median_scale(const float2 *spec, int64_t spitch, int64_t half, int nseries,
-                               float *scale, double *norm, hipStream_t st);
+                               float *scale, double *norm, void *scratch, hipStream_t st);
 // scale[0..nseries) = value (the fixed-variance normalisation).
 hipError_t launch_fill_scale(float *scale, int nseries, float value, hipStream_t st);
 

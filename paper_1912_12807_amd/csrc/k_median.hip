@@ -4,88 +4,127 @@
 // M' = N/2 - 1 powers |A_k|^2, k = 1..N/2-1 (the median of a unit exponential
 // is ln 2, so white-noise powers become unit-mean). The order statistic is
 // found exactly by a three-pass radix select on the IEEE bits of the
-// non-negative float32 powers (bits 30..20, 19..9, 8..0): each pass builds an
-// LDS histogram of the values that share the prefix found so far and picks
-// the bucket that holds the wanted rank. One workgroup per series.
+// non-negative float32 powers (bits 30..20, 19..9, 8..0): each pass counts the
+// values that share the prefix found so far into buckets of the next bits and
+// keeps the bucket that holds the wanted rank.
+//
+// A pass is spread over the whole chip: every workgroup histograms one chunk
+// of one series in LDS and adds its non-zero buckets to the series' global
+// histogram; a one-wave-per-series kernel then selects the bucket, advances
+// the prefix and the rank, and clears the histogram for the next pass.
 #include "dft_small.h"
 #include "fdas_internal.h"
 
 namespace fdas {
 
-static constexpr int kMedThreads = 1024;
+static constexpr int kHistThreads = 256;
+static constexpr int kHistChunk = 8192;     // powers per histogram workgroup
+static constexpr int kBins = 2048;
 
 __device__ __forceinline__ uint32_t power_bits(float2 a) {
     return __float_as_uint(__fmaf_rn(a.x, a.x, __fmul_rn(a.y, a.y)));
 }
 
-__global__ __launch_bounds__(kMedThreads) void k_median_scale(const float2 *__restrict__ spec,
-                                                              int64_t spitch, int64_t half,
-                                                              float *__restrict__ scale,
-                                                              double *__restrict__ norm) {
-    __shared__ uint32_t hist[2048];
-    __shared__ uint32_t s_bucket;
-    __shared__ uint32_t s_below;
-    const float2 *A = spec + (int64_t)blockIdx.x * spitch;
-    const int tid = threadIdx.x;
-    const int64_t count = half - 1;                 // bins 1..half-1
-    uint32_t rank = (uint32_t)((count - 1) / 2);
-    uint32_t prefix = 0, pmask = 0;
-    const int shifts[3] = {20, 9, 0};
-    const int widths[3] = {11, 11, 9};
-    for (int pass = 0; pass < 3; ++pass) {
-        const int sh = shifts[pass];
-        const int nb = 1 << widths[pass];
-        for (int i = tid; i < nb; i += kMedThreads) hist[i] = 0;
-        __syncthreads();
-        for (int64_t k = 1 + tid; k < half; k += kMedThreads) {
-            uint32_t u = power_bits(A[k]);
-            if ((u & pmask) == prefix) atomicAdd(&hist[(u >> sh) & (nb - 1)], 1u);
-        }
-        __syncthreads();
-        if (tid < 64) {
-            // lane l owns bins [l*per, (l+1)*per)
-            const int per = nb / 64;
-            uint32_t local = 0;
-            for (int i = 0; i < per; ++i) local += hist[tid * per + i];
-            uint32_t incl = local;
-            for (int off = 1; off < 64; off <<= 1) {
-                uint32_t v = __shfl_up(incl, off, 64);
-                if (tid >= off) incl += v;
-            }
-            const uint32_t excl = incl - local;
-            const bool mine = (excl <= rank) && (rank < incl);
-            if (mine) {
-                uint32_t acc = excl;
-                for (int i = 0; i < per; ++i) {
-                    uint32_t h = hist[tid * per + i];
-                    if (rank < acc + h) {
-                        s_bucket = (uint32_t)(tid * per + i);
-                        s_below = acc;
-                        break;
-                    }
-                    acc += h;
-                }
-            }
-        }
-        __syncthreads();
-        prefix |= s_bucket << sh;
-        pmask |= (uint32_t)(nb - 1) << sh;
-        rank -= s_below;
-        __syncthreads();
+// state[b] = {prefix, mask, rank, 0}; hist[b][*] = 0.
+__global__ __launch_bounds__(256) void k_med_init(uint32_t *__restrict__ hist, uint4 *__restrict__ state,
+                                                  int64_t half) {
+    const int b = blockIdx.x;
+    for (int i = threadIdx.x; i < kBins; i += blockDim.x) hist[(int64_t)b * kBins + i] = 0;
+    if (threadIdx.x == 0) state[b] = make_uint4(0u, 0u, (uint32_t)((half - 2) / 2), 0u);
+}
+
+// Histogram of bits [sh, sh + width) of the powers in one chunk of bins 1..half-1
+// whose higher bits equal the series' prefix.
+__global__ __launch_bounds__(kHistThreads) void k_med_hist(const float2 *__restrict__ spec, int64_t spitch,
+                                                           int64_t half, const uint4 *__restrict__ state,
+                                                           uint32_t *__restrict__ hist, int sh, int width) {
+    __shared__ uint32_t h[kBins];
+    const int b = blockIdx.y;
+    const int nb = 1 << width;
+    for (int i = threadIdx.x; i < nb; i += kHistThreads) h[i] = 0;
+    __syncthreads();
+    const uint4 s = state[b];
+    const float2 *A = spec + (int64_t)b * spitch;
+    const int64_t k0 = 1 + (int64_t)blockIdx.x * kHistChunk;
+    const int64_t k1 = min(half, k0 + kHistChunk);
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += kHistThreads) {
+        const uint32_t u = power_bits(A[k]);
+        if ((u & s.y) == s.x) atomicAdd(&h[(u >> sh) & (nb - 1)], 1u);
     }
-    if (tid == 0) {
-        const float med = __uint_as_float(prefix);
-        const double nrm = (double)med / 0.69314718055994530942;
-        norm[blockIdx.x] = nrm;
-        scale[blockIdx.x] = med > 0.0f ? (float)sqrt(1.0 / nrm) : 0.0f;
+    __syncthreads();
+    uint32_t *g = hist + (int64_t)b * kBins;
+    for (int i = threadIdx.x; i < nb; i += kHistThreads) {
+        const uint32_t v = h[i];
+        if (v) atomicAdd(&g[i], v);
     }
 }
 
+// One wave per series: the bucket that holds the rank; on the last pass the
+// median is complete and the scale is written.
+__global__ __launch_bounds__(64) void k_med_select(uint32_t *__restrict__ hist, uint4 *__restrict__ state,
+                                                   int sh, int width, int last, float *__restrict__ scale,
+                                                   double *__restrict__ norm) {
+    __shared__ uint32_t s_bucket, s_below;
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int nb = 1 << width;
+    const int per = nb / 64;
+    uint32_t *g = hist + (int64_t)b * kBins;
+    const uint4 s = state[b];
+    uint32_t local = 0;
+    for (int i = 0; i < per; ++i) local += g[lane * per + i];
+    uint32_t incl = local;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    const uint32_t excl = incl - local;
+    if (excl <= s.z && s.z < incl) {
+        uint32_t acc = excl;
+        for (int i = 0; i < per; ++i) {
+            const uint32_t c = g[lane * per + i];
+            if (s.z < acc + c) {
+                s_bucket = (uint32_t)(lane * per + i);
+                s_below = acc;
+                break;
+            }
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < kBins; i += 64) g[i] = 0;
+    if (lane == 0) {
+        const uint32_t prefix = s.x | (s_bucket << sh);
+        const uint32_t mask = s.y | ((uint32_t)(nb - 1) << sh);
+        state[b] = make_uint4(prefix, mask, s.z - s_below, 0u);
+        if (last) {
+            const float med = __uint_as_float(prefix);
+            const double nrm = (double)med / 0.69314718055994530942;
+            norm[b] = nrm;
+            scale[b] = med > 0.0f ? (float)sqrt(1.0 / nrm) : 0.0f;
+        }
+    }
+}
+
+size_t median_scratch_bytes(int nseries) {
+    return (size_t)nseries * (kBins * sizeof(uint32_t) + sizeof(uint4));
+}
+
 hipError_t launch_median_scale(const float2 *spec, int64_t spitch, int64_t half, int nseries,
-                               float *scale, double *norm, hipStream_t st) {
-    if (half < 2 || nseries < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_median_scale, dim3(nseries), dim3(kMedThreads), 0, st, spec, spitch, half,
-                       scale, norm);
+                               float *scale, double *norm, void *scratch, hipStream_t st) {
+    if (half < 2 || nseries < 1 || nseries > 65535) return hipErrorInvalidValue;
+    uint32_t *hist = static_cast<uint32_t *>(scratch);
+    uint4 *state = reinterpret_cast<uint4 *>(hist + (size_t)nseries * kBins);
+    hipLaunchKernelGGL(k_med_init, dim3(nseries), dim3(256), 0, st, hist, state, half);
+    const int64_t nchunk = (half - 1 + kHistChunk - 1) / kHistChunk;
+    const int shifts[3] = {20, 9, 0};
+    const int widths[3] = {11, 11, 9};
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_med_hist, dim3((unsigned)nchunk, nseries), dim3(kHistThreads), 0, st, spec, spitch,
+                           half, state, hist, shifts[pass], widths[pass]);
+        hipLaunchKernelGGL(k_med_select, dim3(nseries), dim3(64), 0, st, hist, state, shifts[pass], widths[pass],
+                           pass == 2 ? 1 : 0, scale, norm);
+    }
     return hipGetLastError();
 }
 
