@@ -13,3 +13,7 @@ are listed, one by one, with the design notes of the repository.
 """
 from .fdas_oracle import *  # noqa: F401,F403
 from .fdas_oracle import __all__  # noqa: F401
+from .refine_oracle import *  # noqa: F401,F403
+from .refine_oracle import __all__ as _refine_all  # noqa: F401
+
+__all__ = list(__all__) + list(_refine_all)
