@@ -153,6 +153,62 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
 fdas_status fdas_tuning_export(fdas_plan p, char *buf, int64_t cap, int64_t *len);
 fdas_status fdas_tuning_import(fdas_plan p, const char *text);
 
+/* ------------------------------------------------------------------ refinement
+ *
+ * Refinement maximises the correlation power of a candidate over continuous
+ * (r, z) near its grid cell (the search of the paper's Section 2, steps 4-5,
+ * reports grid cells only). For a point with window (k0, m) on the normalised
+ * spectrum a_k (a_k = 0 outside bins 1..nbins-1):
+ *   c(r, z) = sum_{k=k0-m}^{k0+m} a_k conj rho(r - k, z),   P = |c|^2,
+ *   rho(q, z) = int_0^1 exp(2 pi i [q u + z (u^2 - u)/2]) du,
+ * the window staying fixed while (r, z) move, so that P is smooth in (r, z).
+ */
+typedef struct {
+    int32_t series;   /* spectrum row */
+    int32_t m;        /* window half-width, 0 <= m <= max_m <= 2000 */
+    int64_t k0;       /* window centre bin; |r - k0| <= 64 */
+    double  r;        /* Fourier frequency in bins (mid-observation) */
+    double  z;        /* drift in bins over the observation, |z| <= 8192 */
+} fdas_refine_point;
+
+/* P, dP/dr and dP/dz of n points (all device arrays). spec_dev: complex64
+ * [nseries][spitch] (interleaved re, im) spectra; scale_dev (may be NULL):
+ * float [nseries], a_k = scale[series] * spec[series][k]. power_dev receives P,
+ * dpdr_dev / dpdz_dev (may be NULL) the derivatives. Points whose fields are
+ * out of range (series, m > max_m, |r - k0|, |z|) receive NaN. */
+fdas_status fdas_refine_eval(const float *spec_dev, int64_t spitch, int64_t nbins, int32_t nseries,
+                             const float *scale_dev, const fdas_refine_point *pts_dev, int64_t n,
+                             int32_t max_m, float *power_dev, float *dpdr_dev, float *dpdz_dev,
+                             void *stream);
+
+/* Backward of fdas_refine_eval for upstream gradients grad_power_dev [n]:
+ * grad_r = g dP/dr, grad_z = g dP/dz (each may be NULL) and, if grad_spec_dev
+ * is not NULL, adds g dP/dRe(spec_k) + i g dP/dIm(spec_k) = 2 g s c rho(r - k, z)
+ * to grad_spec_dev (complex64 [nseries][spitch], same layout as spec_dev) for
+ * every window bin in 1..nbins-1 (atomically: points may share bins). */
+fdas_status fdas_refine_grad(const float *spec_dev, int64_t spitch, int64_t nbins, int32_t nseries,
+                             const float *scale_dev, const fdas_refine_point *pts_dev, int64_t n,
+                             int32_t max_m, const float *grad_power_dev, float *grad_r_dev,
+                             float *grad_z_dev, float *grad_spec_dev, void *stream);
+
+/* Refine n candidates of a batch of series: the plan computes the normalised
+ * spectra of series_dev (device float32 [nseries][nsamp]) as fdas_search does,
+ * then runs, per point, iters steps of
+ *   (r, z) += (3/(2 pi^2) dP/dr, 90/pi^2 dP/dz) / P
+ * (the Newton step at a peak of |rho|^2, whose curvatures in r and z are
+ * -2 pi^2/3 and -pi^2/90 per unit power), clamped to |r - r0| <= 1 and
+ * |z - z0| <= 2 dz around the start (r0, z0). pts_host (host, n entries): on
+ * input series, r and z of each start; k0 = nearest bin to r0 and
+ * m = ceil((|z0| + 2 dz)/2) + K + 1 are set by the call; on output r and z hold
+ * the refined point. power_host (host, n floats) receives P there. */
+fdas_status fdas_refine(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries, double dz,
+                        int32_t iters, fdas_refine_point *pts_host, float *power_host, int64_t n,
+                        void *stream);
+
+/* The window fdas_refine uses for a start (r0, z0): k0 = floor(r0 + 1/2),
+ * m = ceil((|z0| + 2 dz)/2) + K + 1 (host, no device work). */
+fdas_status fdas_refine_window(double r0, double z0, double dz, int32_t K, int64_t *k0, int32_t *m);
+
 /* The normalised power plane of each series: plane_dev (device, float32)
  * receives [nseries][NZ][NR] with NZ = 2 zmax/dz + 1 rows (z = (row - zmax/dz)
  * dz) and NR = nsamp - 2 rlo columns (column c holds R = c + 2 rlo).
@@ -212,9 +268,10 @@ fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out);
  * the summed device milliseconds and launches[i] the number of timed
  * launches of phase i since the last reset (both arrays hold FDAS_NPHASES
  * entries, either may be NULL). Phases: 0 real FFT, 1 normalisation,
- * 2 power plane, 3 harmonic sums, 4 compaction, 5 drift argmax, 6 copy-out.
+ * 2 power plane, 3 harmonic sums, 4 compaction, 5 drift argmax, 6 copy-out,
+ * 7 refinement.
  * reset != 0 clears the totals after reading. */
-#define FDAS_NPHASES 7
+#define FDAS_NPHASES 8
 fdas_status fdas_profile_read(fdas_plan p, double *ms, int64_t *launches, int32_t reset);
 
 /* Description of a status code (static storage). */

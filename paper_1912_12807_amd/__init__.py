@@ -27,8 +27,9 @@ EXPORTED = (
     "fdas_harmsum", "fdas_spectrum", "fdas_geometry", "fdas_threshold", "fdas_sigma",
     "fdas_template_taps", "fdas_status_string", "fdas_last_error", "fdas_profile_read",
     "fdas_plan_get_info", "fdas_search_ragged", "fdas_tuning_export", "fdas_tuning_import",
+    "fdas_refine_eval", "fdas_refine_grad", "fdas_refine", "fdas_refine_window",
 )
-PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "argmax", "copyout")
+PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "argmax", "copyout", "refine")
 
 
 class PlanOpts(ctypes.Structure):
@@ -51,6 +52,8 @@ CAND_DTYPE = np.dtype([("series", "<i4"), ("harm", "<i4"), ("r_idx", "<i8"), ("z
                        ("power", "<f4"), ("sigma", "<f8"), ("r_fund", "<f8"), ("z_fund", "<f8"),
                        ("f_hz", "<f8"), ("fdot_hz_s", "<f8")], align=True)
 assert CAND_DTYPE.itemsize == 64
+REFINE_DTYPE = np.dtype([("series", "<i4"), ("m", "<i4"), ("k0", "<i8"), ("r", "<f8"), ("z", "<f8")])
+assert REFINE_DTYPE.itemsize == 32
 
 
 class FdasError(RuntimeError):
@@ -119,6 +122,16 @@ def load(path: Optional[str] = None):
     lib.fdas_tuning_export.restype = c.c_int
     lib.fdas_tuning_import.argtypes = [P, c.c_char_p]
     lib.fdas_tuning_import.restype = c.c_int
+    lib.fdas_refine_eval.argtypes = [P, c.c_int64, c.c_int64, c.c_int32, P, P, c.c_int64, c.c_int32, P, P, P, P]
+    lib.fdas_refine_eval.restype = c.c_int
+    lib.fdas_refine_grad.argtypes = [P, c.c_int64, c.c_int64, c.c_int32, P, P, c.c_int64, c.c_int32, P, P, P, P,
+                                     P]
+    lib.fdas_refine_grad.restype = c.c_int
+    lib.fdas_refine.argtypes = [P, P, c.c_int64, c.c_int32, c.c_double, c.c_int32, P, P, c.c_int64, P]
+    lib.fdas_refine.restype = c.c_int
+    lib.fdas_refine_window.argtypes = [c.c_double, c.c_double, c.c_double, c.c_int32, c.POINTER(c.c_int64),
+                                       c.POINTER(c.c_int32)]
+    lib.fdas_refine_window.restype = c.c_int
     _lib = lib
     return lib
 
@@ -254,6 +267,25 @@ class Plan:
         if st != FDAS_OK:
             self._raise(st, "fdas_tuning_import")
 
+    def refine(self, t, r0, z0, series=None, dz: float = None, iters: int = 20, stream=None):
+        """Refine start points (r0, z0) [bins] of series ``series`` of the CUDA float32
+        [B][N] batch t; returns (r, z, power) as float64, float64, float32 arrays."""
+        t = _check_series(t)
+        r0 = np.atleast_1d(np.asarray(r0, dtype=np.float64))
+        n = r0.shape[0]
+        pts = np.zeros(n, dtype=REFINE_DTYPE)
+        pts["r"] = r0
+        pts["z"] = np.broadcast_to(np.asarray(z0, dtype=np.float64), (n,))
+        pts["series"] = 0 if series is None else np.broadcast_to(np.asarray(series, dtype=np.int32), (n,))
+        power = np.zeros(n, dtype=np.float32)
+        dz = self.dz if dz is None else dz
+        st = self.lib.fdas_refine(self.handle, ctypes.c_void_p(t.data_ptr()), t.shape[1], t.shape[0], float(dz),
+                                  int(iters), pts.ctypes.data_as(ctypes.c_void_p),
+                                  power.ctypes.data_as(ctypes.c_void_p), n, _stream_handle(stream))
+        if st != FDAS_OK:
+            self._raise(st, "fdas_refine")
+        return pts["r"].copy(), pts["z"].copy(), power
+
     def harmsum(self, plane, nsamp: int, tsamp: float, zmax: float = None, dz: float = None,
                 numharm: int = None, sigma: float = 6.0, cap: int = 1 << 16, stream=None):
         """Candidates of a caller-built plane (CUDA float32 [B][NZ][NR])."""
@@ -358,3 +390,90 @@ def search(t, tsamp: float, zmax: float, dz: float, numharm: int, sigma: float =
         return plan.search(t, tsamp, zmax, dz, numharm, sigma, cap=cap, stream=stream)
     finally:
         plan.close()
+
+
+def refine_window(r0: float, z0: float, dz: float, K: int = 16):
+    """(k0, m): the refinement window the library uses for a start (r0, z0)."""
+    k0, m = ctypes.c_int64(), ctypes.c_int32()
+    st = load().fdas_refine_window(float(r0), float(z0), float(dz), int(K), ctypes.byref(k0), ctypes.byref(m))
+    if st != FDAS_OK:
+        raise FdasError(st, "fdas_refine_window: window out of range")
+    return k0.value, m.value
+
+
+def _refine_points(series, k0, m, r, z):
+    """Pack per-point fields (CUDA tensors) into the library's 32-byte point records."""
+    import torch
+    n = r.shape[0]
+    pts = torch.empty((n, 4), dtype=torch.int64, device=r.device)
+    pts[:, 0] = (m.to(torch.int64) << 32) | (series.to(torch.int64) & 0xFFFFFFFF)
+    pts[:, 1] = k0.to(torch.int64)
+    pts[:, 2] = r.to(torch.float64).contiguous().view(torch.int64)
+    pts[:, 3] = z.to(torch.float64).contiguous().view(torch.int64)
+    return pts
+
+
+def _refine_autograd():
+    import torch
+
+    class RefinePower(torch.autograd.Function):
+        """P(r, z) of the refinement objective with hand-written backward kernels."""
+
+        @staticmethod
+        def forward(ctx, spec, r, z, series, k0, m, max_m):
+            lib = load()
+            spec = spec.contiguous()
+            pts = _refine_points(series, k0, m, r, z)
+            n = r.shape[0]
+            power = torch.empty(n, dtype=torch.float32, device=r.device)
+            st = lib.fdas_refine_eval(ctypes.c_void_p(spec.data_ptr()), spec.shape[1], spec.shape[1] - 1,
+                                      spec.shape[0], None, ctypes.c_void_p(pts.data_ptr()), n, int(max_m),
+                                      ctypes.c_void_p(power.data_ptr()), None, None, _stream_handle())
+            if st != FDAS_OK:
+                raise FdasError(st, f"fdas_refine_eval: {lib.fdas_status_string(st).decode()}")
+            ctx.save_for_backward(spec, pts)
+            ctx.max_m = int(max_m)
+            ctx.rdtype, ctx.zdtype = r.dtype, z.dtype
+            return power
+
+        @staticmethod
+        def backward(ctx, grad_power):
+            lib = load()
+            spec, pts = ctx.saved_tensors
+            n = pts.shape[0]
+            g = grad_power.to(torch.float32).contiguous()
+            gr = torch.empty(n, dtype=torch.float32, device=g.device)
+            gz = torch.empty(n, dtype=torch.float32, device=g.device)
+            gs = torch.zeros_like(spec) if ctx.needs_input_grad[0] else None
+            st = lib.fdas_refine_grad(ctypes.c_void_p(spec.data_ptr()), spec.shape[1], spec.shape[1] - 1,
+                                      spec.shape[0], None, ctypes.c_void_p(pts.data_ptr()), n, ctx.max_m,
+                                      ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(gr.data_ptr()),
+                                      ctypes.c_void_p(gz.data_ptr()),
+                                      ctypes.c_void_p(gs.data_ptr()) if gs is not None else None,
+                                      _stream_handle())
+            if st != FDAS_OK:
+                raise FdasError(st, f"fdas_refine_grad: {lib.fdas_status_string(st).decode()}")
+            return gs, gr.to(ctx.rdtype), gz.to(ctx.zdtype), None, None, None, None
+
+    return RefinePower
+
+
+_REFINE_FN = None
+
+
+def refine_power(spec, r, z, series, k0, m, max_m: int = None):
+    """Differentiable refinement objective on the GPU.
+
+    spec: CUDA complex64 [B][N/2+1] normalised spectra (bins 0..N/2; DC and
+    Nyquist are not read); r, z: CUDA float64 [n] points (bins); series, k0, m:
+    CUDA integer [n] window of each point. Returns P (float32 [n]); gradients
+    flow to spec, r and z through the library's backward kernel."""
+    global _REFINE_FN
+    if _REFINE_FN is None:
+        _REFINE_FN = _refine_autograd()
+    import torch
+    if not (isinstance(spec, torch.Tensor) and spec.is_cuda and spec.dtype == torch.complex64 and spec.dim() == 2):
+        raise TypeError("spec must be a CUDA complex64 [B][N/2+1] tensor")
+    if max_m is None:
+        max_m = int(m.max().item()) if m.numel() else 0
+    return _REFINE_FN.apply(torch.view_as_real(spec.contiguous()), r, z, series, k0, m, max_m)

@@ -161,6 +161,10 @@ struct fdas_plan_s {
     DevCand *h_rec = nullptr;
     int64_t h_rec_cap = 0;
     int64_t *h_offs = nullptr;
+    // refinement points
+    fdas_refine_point *d_rpts = nullptr, *h_rpts = nullptr;
+    float *d_rpow = nullptr, *h_rpow = nullptr;
+    int64_t rpts_cap = 0;
 
     // graph replay
     hipStream_t cap_st = nullptr;   // private stream that captures (never executes) the launches
@@ -831,7 +835,7 @@ void fdas_plan_destroy(fdas_plan p) {
     for (auto &b : p->banks) (void)hipFree(b.d);
     for (auto &t : p->tables) (void)hipFree(t.d);
     void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_med, p->d_thr, p->d_state, p->d_offs,
-                   p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr};
+                   p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow};
     for (void *q : dev)
         if (q) (void)hipFree(q);
     for (auto &t : p->ev_pending) {
@@ -839,7 +843,7 @@ void fdas_plan_destroy(fdas_plan p) {
         p->ev_pool.push_back(std::get<2>(t));
     }
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-    void *host[] = {p->h_state, p->h_small, p->h_rec, p->h_offs};
+    void *host[] = {p->h_state, p->h_small, p->h_rec, p->h_offs, p->h_rpts, p->h_rpow};
     for (void *q : host)
         if (q) (void)hipHostFree(q);
     if (cur >= 0) (void)hipSetDevice(cur);
@@ -1033,6 +1037,98 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
         << p->rec_cap;
     for (const auto &G : B.groups) key_group(key, G);
     return run_batch(p, series_dev, true, B, dz, numharm, key.str(), out_host, cap, n_total, st);
+}
+
+fdas_status fdas_refine_window(double r0, double z0, double dz, int32_t K, int64_t *k0, int32_t *m) {
+    if (!k0 || !m || !std::isfinite(r0) || !std::isfinite(z0) || !(dz > 0) || !std::isfinite(dz) || K < 0 ||
+        K > 1024 || std::fabs(r0) > 9e15)
+        return FDAS_E_INVAL;
+    const double mm = std::ceil((std::fabs(z0) + 2.0 * dz) / 2.0) + K + 1;
+    if (mm > kRefineMaxM) return FDAS_E_INVAL;
+    *k0 = (int64_t)std::floor(r0 + 0.5);
+    *m = (int32_t)mm;
+    return FDAS_OK;
+}
+
+static fdas_status check_refine_args(const float *spec, int64_t spitch, int64_t nbins, int32_t nseries,
+                                     const fdas_refine_point *pts, int64_t n, int32_t max_m) {
+    if (!spec || ((uintptr_t)spec & 7) || !pts || ((uintptr_t)pts & 7) || nbins < 2 || spitch < nbins ||
+        nseries < 1 || n < 0 || n > 0x7fffffffLL || max_m < 0 || max_m > kRefineMaxM)
+        return FDAS_E_INVAL;
+    return FDAS_OK;
+}
+
+fdas_status fdas_refine_eval(const float *spec_dev, int64_t spitch, int64_t nbins, int32_t nseries,
+                             const float *scale_dev, const fdas_refine_point *pts_dev, int64_t n,
+                             int32_t max_m, float *power_dev, float *dpdr_dev, float *dpdz_dev,
+                             void *stream) {
+    TRY(check_refine_args(spec_dev, spitch, nbins, nseries, pts_dev, n, max_m));
+    if (!power_dev) return FDAS_E_INVAL;
+    if (n == 0) return FDAS_OK;
+    const hipError_t e = launch_refine_eval(reinterpret_cast<const float2 *>(spec_dev), spitch, nbins, nseries,
+                                            scale_dev, pts_dev, n, max_m, power_dev, dpdr_dev, dpdz_dev,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FDAS_OK : FDAS_E_DEVICE;
+}
+
+fdas_status fdas_refine_grad(const float *spec_dev, int64_t spitch, int64_t nbins, int32_t nseries,
+                             const float *scale_dev, const fdas_refine_point *pts_dev, int64_t n,
+                             int32_t max_m, const float *grad_power_dev, float *grad_r_dev,
+                             float *grad_z_dev, float *grad_spec_dev, void *stream) {
+    TRY(check_refine_args(spec_dev, spitch, nbins, nseries, pts_dev, n, max_m));
+    if (!grad_power_dev || ((uintptr_t)grad_spec_dev & 7)) return FDAS_E_INVAL;
+    if (n == 0) return FDAS_OK;
+    const hipError_t e = launch_refine_grad(reinterpret_cast<const float2 *>(spec_dev), spitch, nbins, nseries,
+                                            scale_dev, pts_dev, n, max_m, grad_power_dev, grad_r_dev, grad_z_dev,
+                                            grad_spec_dev, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FDAS_OK : FDAS_E_DEVICE;
+}
+
+fdas_status fdas_refine(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries, double dz,
+                        int32_t iters, fdas_refine_point *pts_host, float *power_host, int64_t n,
+                        void *stream) {
+    TRY(check_plan(p));
+    if (!series_dev || ((uintptr_t)series_dev & 7)) return p->fail(FDAS_E_INVAL, "series pointer NULL or misaligned");
+    if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
+    if (nsamp < 8 || (nsamp & 1) || nsamp > p->max_nsamp)
+        return p->fail(FDAS_E_INVAL, "nsamp odd, below 8 or above the plan's max_nsamp");
+    if (!pow2(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp must be a power of two");
+    if (!(dz > 0) || !std::isfinite(dz) || iters < 0 || iters > 10000 || n < 0 || n > 0x7fffffffLL ||
+        (n > 0 && (!pts_host || !power_host)))
+        return p->fail(FDAS_E_INVAL, "bad dz, iters or point arrays");
+    if (n == 0) return FDAS_OK;
+    int32_t max_m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        fdas_refine_point &q = pts_host[i];
+        if (q.series < 0 || q.series >= nseries || !std::isfinite(q.r) || !std::isfinite(q.z) ||
+            std::fabs(q.z) + 2.0 * dz > 8192.0 || q.r < 0.0 || q.r > (double)(nsamp / 2))
+            return p->fail(FDAS_E_INVAL, "refinement start out of range (series, r in 0..nsamp/2, |z|)");
+        if (fdas_refine_window(q.r, q.z, dz, p->opts.K, &q.k0, &q.m) != FDAS_OK)
+            return p->fail(FDAS_E_INVAL, "refinement window too wide for this drift");
+        max_m = std::max(max_m, q.m);
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n > p->rpts_cap) {
+        TRY(dalloc(p, &p->d_rpts, n, "refinement points"));
+        TRY(dalloc(p, &p->d_rpow, n, "refinement powers"));
+        TRY(halloc(p, &p->h_rpts, n, "refinement points"));
+        TRY(halloc(p, &p->h_rpow, n, "refinement powers"));
+        p->rpts_cap = n;
+    }
+    std::memcpy(p->h_rpts, pts_host, (size_t)n * sizeof(fdas_refine_point));
+    TRY(run_spectrum(p, series_dev, nullptr, nsamp, nseries, 0, st));
+    HIPTRY(p, hipMemcpyAsync(p->d_rpts, p->h_rpts, n * sizeof(fdas_refine_point), hipMemcpyHostToDevice, st));
+    hipEvent_t e = p->begin(st);
+    HIPTRY(p, launch_refine_ascent(p->d_spec, p->spitch, nsamp / 2, nseries, p->d_scale, p->d_rpts, n, max_m, dz,
+                                   iters, p->d_rpow, st));
+    p->end(7, e, st);
+    HIPTRY(p, hipMemcpyAsync(p->h_rpts, p->d_rpts, n * sizeof(fdas_refine_point), hipMemcpyDeviceToHost, st));
+    HIPTRY(p, hipMemcpyAsync(p->h_rpow, p->d_rpow, n * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPTRY(p, hipStreamSynchronize(st));
+    p->collect();
+    std::memcpy(pts_host, p->h_rpts, (size_t)n * sizeof(fdas_refine_point));
+    std::memcpy(power_host, p->h_rpow, (size_t)n * sizeof(float));
+    return FDAS_OK;
 }
 
 fdas_status fdas_plane(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,

@@ -27,6 +27,12 @@ double log_gauss_tail(double s);
 double threshold(int H, double sigma);
 double sigma_of(int H, double power);
 
+// 16-point Gauss-Legendre nodes and weights on [-1, 1] (FP64, Newton on P_16).
+struct GaussLegendre16 {
+    double x[16], w[16];
+};
+const GaussLegendre16 &gauss_legendre16();
+
 // ---------------------------------------------------------------- device records
 // One thresholded column maximum, in (series, stage, column) order.
 struct DevCand {
@@ -141,5 +147,19 @@ hipError_t launch_compact(const float *maxv, int64_t nelem, int64_t mpitch, int 
 hipError_t launch_argmax(const float *plane, int64_t pitch, int64_t series_stride, int64_t rlo,
                          int Z, int numharm, int b0, DevCand *rec, const int64_t *state,
                          int64_t cap, hipStream_t st);
+
+// K7/K8: refinement objective (see fdas_refine_eval), its gradients and the
+// ascent. One wave per point; the window of 2 m + 1 bins is staged in LDS, so
+// every point must have m <= max_m <= kRefineMaxM (others give NaN).
+constexpr int kRefineMaxM = 2000;
+hipError_t launch_refine_eval(const float2 *spec, int64_t spitch, int64_t nbins, int nseries, const float *scale,
+                              const fdas_refine_point *pts, int64_t n, int max_m, float *power, float *dpdr,
+                              float *dpdz, hipStream_t st);
+hipError_t launch_refine_grad(const float2 *spec, int64_t spitch, int64_t nbins, int nseries, const float *scale,
+                              const fdas_refine_point *pts, int64_t n, int max_m, const float *grad_power,
+                              float *grad_r, float *grad_z, float *grad_spec, hipStream_t st);
+hipError_t launch_refine_ascent(const float2 *spec, int64_t spitch, int64_t nbins, int nseries, const float *scale,
+                                fdas_refine_point *pts, int64_t n, int max_m, double dz, int iters, float *power,
+                                hipStream_t st);
 
 }  // namespace fdas

@@ -68,6 +68,19 @@ static const GaussLegendre &gl16() {
     return g;
 }
 
+const GaussLegendre16 &gauss_legendre16() {
+    static const GaussLegendre16 t = [] {
+        GaussLegendre16 r;
+        const GaussLegendre &g = gl16();
+        for (int i = 0; i < 16; ++i) {
+            r.x[i] = g.x[i];
+            r.w[i] = g.w[i];
+        }
+        return r;
+    }();
+    return t;
+}
+
 // ---------------------------------------------------------------- Fresnel integral F(x)
 
 // int_a^b exp(i pi t^2 / 2) dt by composite 16-point Gauss-Legendre, panels <= 0.25 wide.
