@@ -219,11 +219,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4))
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4, 5))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
+    ap.add_argument("--autotune", type=int, default=0, choices=(0, 1),
                     help="time candidate launch parameters on the first search (during warmup)")
+    ap.add_argument("--seg-len", type=int, default=0, help="plan option seg_len (0: the plan's choice)")
+    ap.add_argument("--harm-block", type=int, default=0, help="plan option harm_block (0: default)")
+    ap.add_argument("--harm-pair", type=int, default=0, choices=(0, 1), help="plan option harm_pair")
+    ap.add_argument("--tuning", default="",
+                    help="launch parameters to preload, tuning lines separated by ';' (no tuning for those shapes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("STATS_CSV", "OUT_MD", "COMMAND"),
@@ -266,12 +271,17 @@ def main():
     fdas.load()
     if args.config == 4:
         return bench_ragged(args)
+    if args.config == 5:
+        return bench_refine(args)
     wl = _workload(args.config)
     print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
     x = torch.from_numpy(synth.generate(wl)).cuda()
     rlo, nr, nz = fdas.geometry(wl.nsamp, wl.tsamp, wl.zmax, wl.dz)
     cells = wl.nseries * nr * nz
-    plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1, autotune=args.autotune)
+    plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1, autotune=args.autotune,
+                     seg_len=args.seg_len, harm_block=args.harm_block, harm_pair=args.harm_pair)
+    if args.tuning:
+        plan.load_tuning(args.tuning.replace(";", "\n"))
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -421,6 +431,8 @@ def bench_ragged(args):
         return (time.perf_counter() - t0) / steps, c
 
     plan = fdas.Plan(nmax, wl.nseries, zmax, wl.dz, wl.numharm, autotune=1, graph=1)
+    if args.tuning:
+        plan.load_tuning(args.tuning.replace(";", "\n"))
     print(f"[bench] warmup {args.warmup} (autotune, graph capture)", file=sys.stderr, flush=True)
     for _ in range(max(1, args.warmup)):
         cands = call(plan)
@@ -500,6 +512,111 @@ def bench_ragged(args):
         "phases_ms": {k: round(v[0] / 2, 4) for k, v in ph.items()},
         "tuning": tuning.strip().split("\n"),
         "candidates": int(len(cands)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _oracle_refine(args):
+    import oracle as O
+    import synth
+    starts, dz = args
+    wl = synth.config1()
+    Ah = O.normalise(O.spectrum(synth.generate(wl)[0]))[0]
+    t0 = time.perf_counter()
+    for r0, z0 in starts:
+        O.refine(Ah, r0, z0, dz)
+    return time.perf_counter() - t0
+
+
+def refine_starts_gpu(plane, rlo, Z, count):
+    """The count largest local maxima of a stage-1 plane on its integer-r cells (3x3 on
+    that sub-grid), as (R, Zq) in decreasing power (input preparation with torch ops)."""
+    import torch
+    sub = plane[0][:, 0::2].contiguous()
+    pad = torch.nn.functional.pad(sub[None, None], (1, 1, 1, 1), value=float("-inf"))
+    mx = torch.nn.functional.max_pool2d(pad, 3, stride=1)[0, 0]
+    vals = torch.where(sub >= mx, sub, torch.full_like(sub, float("-inf"))).flatten()
+    top = torch.topk(vals, count)
+    zi = (top.indices // sub.shape[1]).cpu().numpy()
+    ji = (top.indices % sub.shape[1]).cpu().numpy()
+    return [(int(2 * rlo + 2 * j), int(z - Z)) for z, j in zip(zi, ji)]
+
+
+def bench_refine(args):
+    """4096 starts (the largest integer-r local maxima of the single-series plane)
+    refined by 20 ascent steps each, in one fdas_refine call."""
+    import numpy as np
+    import torch
+
+    import paper_1912_12807_amd as fdas
+    import synth
+
+    wl = synth.config1()
+    x = torch.from_numpy(synth.generate(wl)).cuda()
+    rlo, nr, nz = fdas.geometry(wl.nsamp, wl.tsamp, wl.zmax, wl.dz)
+    plan = fdas.Plan(wl.nsamp, 1, wl.zmax, wl.dz, 1, profile=1)
+    starts = refine_starts_gpu(plan.plane(x, wl.tsamp), rlo, nz // 2, 4096)
+    r0 = np.array([s[0] / 2 for s in starts])
+    z0 = np.array([s[1] * wl.dz for s in starts])
+    iters = 20
+    print(f"[bench] refine warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(max(1, args.warmup)):
+        r, z, P = plan.refine(x, r0, z0, iters=iters)
+    plan.profile(reset=True)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r, z, P = plan.refine(x, r0, z0, iters=iters)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    ph = plan.profile(reset=True)
+    k_s = ph["refine"][0] / 1e3 / args.steps
+    # algorithmic work: per evaluation, nodes x (8 FLOP per tap of the Horner sums + per
+    # 16-tap block and node one phase reduction and sincos, counted as 20 FLOP)
+    flops = 0.0
+    for z_ in z0:
+        M = int(math.ceil((abs(z_) + 2 * wl.dz) / 2)) + 16 + 1
+        taps16 = (2 * M + 1 + 15) // 16 * 16
+        npan_est = M + 1 + abs(z_) / 2 + 1
+        flops += (iters + 1) * 16 * math.ceil(npan_est) * (8 * taps16 + 20 * taps16 / 16 + 30)
+    achieved = flops / k_s / 1e12
+    inj = wl.injections[0]
+    near = np.nonzero((np.abs(r0 - inj.r0) <= 1) & (np.abs(z0 - inj.z0) <= 2 * wl.dz))[0]
+    found = None
+    if near.size:
+        i = int(near[0])
+        found = {"r": float(r[i]), "z": float(z[i]), "power": float(P[i]), "r0": inj.r0, "z0": inj.z0}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+        per = 8
+        sample = [list(zip(r0[i * per:(i + 1) * per], z0[i * per:(i + 1) * per])) for i in range(cores)]
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        t1 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            times = pool.map(_oracle_refine, [(s_, wl.dz) for s_ in sample])
+        wall = time.perf_counter() - t1
+        cpu = {"value": cores * per / wall, "unit": "candidates/s", "cores": cores, "kind": "oracle",
+               "sample": f"the first {cores * per} of the 4096 starts, {per} per process, FP64 oracle "
+                         f"ascent of 20 steps ({wall:.1f} s wall incl. start-up, "
+                         f"{sum(times) / cores:.1f} s of refinement per process)",
+               "cpu": _cpu_model()}
+    out = {
+        "metric": "refined candidates/s (20 ascent steps at fractional r, z)", "value": len(starts) / sec,
+        "unit": "candidates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (phases and node sums f64)", "data": "synthetic",
+        "config": {"workload": "refine-4096-starts-of-1x2^17", "starts": len(starts), "iters": iters,
+                   "nsamp": wl.nsamp, "zmax": wl.zmax, "dz": wl.dz, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK, "kernel": "k_refine_ascent",
+                     "per_unit": f"{flops / len(starts):.3g} FLOP/candidate", "traffic": None,
+                     "launch_ms": 1e3 * k_s},
+        "cpu_baseline": cpu,
+        "injected_signal": found,
+        "phases_ms": {k: round(v[0] / args.steps, 4) for k, v in ph.items()},
     }
     print(json.dumps(out), flush=True)
 
