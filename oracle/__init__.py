@@ -17,3 +17,7 @@ from .refine_oracle import *  # noqa: F401,F403
 from .refine_oracle import __all__ as _refine_all  # noqa: F401
 
 __all__ = list(__all__) + list(_refine_all)
+from .dedisp_oracle import *  # noqa: F401,F403
+from .dedisp_oracle import __all__ as _dedisp_all  # noqa: F401
+
+__all__ = list(__all__) + list(_dedisp_all)

@@ -272,3 +272,89 @@ def small_batch(nseries: int, nsamp: int, tsamp: float, zmax: float, dz: float, 
                              duty=rng.uniform(0.02, 0.10), phase0=rng.uniform(0, 1)))
     return Workload(f"small-{nseries}x{nsamp}", config, nsamp, nseries, tsamp, zmax, dz, numharm,
                     sigma, inj, noise=noise)
+
+
+# --------------------------------------------------------------------------- filterbank data
+
+# Dedispersion plans of the paper: (DM start, DM step, number of DMs, downsampling
+# factor) per range, Table 2 (PMPS) and Table 3 (FAST drift scan).
+DDPLAN_PMPS = [(0.0, 0.5, 228, 1), (114.0, 1.0, 152, 2), (266.0, 2.0, 105, 4), (476.0, 5.0, 76, 8),
+               (856.0, 10.0, 152, 16), (2376.0, 20.0, 76, 32)]
+DDPLAN_FAST = [(0.0, 0.1, 315, 8), (31.5, 0.2, 157, 16), (62.9, 0.5, 153, 32), (139.4, 1.0, 139, 64),
+               (278.4, 2.0, 139, 128), (556.4, 3.0, 76, 128)]
+
+# Signal model of dispersion: a pulse emitted at time t arrives in channel c at
+# t + K DM f_c^-2 (cold plasma, K in MHz^2 s cm^3/pc); only differences between
+# channels matter here, so arrival times are taken relative to the highest channel.
+_DISPERSION_K = 4.148808e3
+
+
+@dataclasses.dataclass
+class DispersedPulsar:
+    period: float        # s
+    dm: float            # pc cm^-3
+    amp: float           # peak height per channel, in raw sample units
+    duty: float          # FWHM as a fraction of the period
+    phase0: float = 0.0  # cycles, at t = 0 in the highest channel
+
+
+@dataclasses.dataclass
+class Filterbank:
+    name: str
+    nchan: int
+    nsamp: int
+    tsamp: float
+    f0: float            # centre frequency of channel 0 (MHz)
+    df: float            # channel spacing (MHz; negative for a descending band)
+    pulsars: List[DispersedPulsar]
+    plan: list           # DM plan ranges (dm_start, dm_step, ndm, downsamp)
+    seed: int
+    mean: float = 100.0
+    sd: float = 10.0
+
+    def freqs(self) -> np.ndarray:
+        return self.f0 + np.arange(self.nchan, dtype=np.float64) * self.df
+
+
+def fast_filterbank(nsamp: int = 1 << 18) -> Filterbank:
+    """FAST drift-scan file shape (Table 1): 200 channels of 0.25 MHz over 290-340 MHz,
+    0.2 ms sampling, 2^18 samples (52.4288 s), 8 bits; three dispersed pulsars."""
+    psr = [DispersedPulsar(0.08731, 12.3, 1.2, 0.05, 0.1), DispersedPulsar(0.31412, 45.6, 2.0, 0.03, 0.6),
+           DispersedPulsar(0.02573, 88.8, 1.0, 0.08, 0.3)]
+    return Filterbank("fast-filterbank-200x2^18", 200, nsamp, 2.0e-4, 290.125, 0.25, psr, DDPLAN_FAST,
+                      seed_for(6, 0))
+
+
+def pmps_filterbank(nsamp: int = 1 << 23) -> Filterbank:
+    """PMPS file shape (Table 1): 96 channels of 3 MHz over 1231.5-1516.5 MHz (descending),
+    250 us sampling, 2^23 samples, 8 bits; two dispersed pulsars."""
+    psr = [DispersedPulsar(0.4471, 180.5, 1.5, 0.04, 0.2), DispersedPulsar(0.00412, 33.3, 0.6, 0.10, 0.7)]
+    return Filterbank("pmps-filterbank-96x2^23", 96, nsamp, 2.5e-4, 1515.0, -3.0, psr, DDPLAN_PMPS,
+                      seed_for(7, 0))
+
+
+def small_filterbank(nchan: int, nsamp: int, tsamp: float, f0: float, df: float, plan, pulsars=(),
+                     config: int = 97) -> Filterbank:
+    return Filterbank(f"filterbank-{nchan}x{nsamp}", nchan, nsamp, tsamp, f0, df, list(pulsars), list(plan),
+                      seed_for(config, 1))
+
+
+def generate_filterbank(fb: Filterbank, block: int = 1 << 16) -> np.ndarray:
+    """uint8 [nsamp][nchan] (time-major, as filterbank files store it): Gaussian noise of
+    the given mean and sd plus von Mises pulse trains delayed per channel by dispersion,
+    rounded to integers and clipped to 0..255. Generated in time blocks."""
+    rng = np.random.Generator(np.random.PCG64(fb.seed))
+    f = fb.freqs()
+    fhi = float(np.max(f))
+    out = np.empty((fb.nsamp, fb.nchan), dtype=np.uint8)
+    for t0 in range(0, fb.nsamp, block):
+        n = min(block, fb.nsamp - t0)
+        x = fb.mean + fb.sd * rng.standard_normal((n, fb.nchan))
+        t = (t0 + np.arange(n, dtype=np.float64))[:, None] * fb.tsamp
+        for p in fb.pulsars:
+            delay = _DISPERSION_K * p.dm * (1.0 / (f * f) - 1.0 / (fhi * fhi))
+            ph = (t - delay[None, :]) / p.period + p.phase0
+            kappa = von_mises_kappa(p.duty)
+            x += p.amp * np.exp(kappa * (np.cos(2.0 * np.pi * ph) - 1.0))
+        out[t0:t0 + n] = np.clip(np.rint(x), 0, 255).astype(np.uint8)
+    return out
