@@ -38,6 +38,9 @@ def test_brute_force_on_tiny_input():
                 if jj < n:
                     for d in range(D):
                         s += int(x[jj * D + d, c])
+                else:                                   # past the end: D times the rounded mean
+                    tot = sum(int(v) for v in x[:, c])
+                    s += D * ((2 * tot + nsamp) // (2 * nsamp))
             assert got[i, j] == s, (i, j)
 
 
@@ -47,6 +50,15 @@ def test_zero_dm_is_the_total_power_series():
     fr = O.channel_freqs(7, 300.0, 2.0)
     out = O.dedisperse(x, fr, 1e-4, [0.0], 4)
     assert np.array_equal(out[0], x.astype(np.int64).reshape(64, 4, 7).sum(axis=(1, 2)))
+
+
+def test_constant_channels_give_constant_series_at_any_dm():
+    # a channel that holds one value everywhere reads the same value past its end,
+    # so every trial DM sees the same flat series
+    x = np.tile(np.arange(7, dtype=np.uint8) * 30 + 3, (512, 1))
+    fr = O.channel_freqs(7, 300.0, 5.0)
+    out = O.dedisperse(x, fr, 1e-3, [0.0, 50.0, 400.0], 4)
+    assert np.all(out == 4 * int(x[0].astype(np.int64).sum()))
 
 
 def test_downsampling_is_hierarchical():
