@@ -153,6 +153,36 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
 fdas_status fdas_tuning_export(fdas_plan p, char *buf, int64_t cap, int64_t *len);
 fdas_status fdas_tuning_import(fdas_plan p, const char *text);
 
+/* ------------------------------------------------------------------ dedispersion
+ *
+ * Incoherent dedispersion of 8-bit filterbank data into time series at trial
+ * DMs (the paper's Section 2, step 2, with DM plans like its Tables 2-3). For
+ * a range with downsampling factor D and trial DM d:
+ *   y_c[j] = sum_{s<D} x[j D + s][c],  j < nsamp / D,
+ *   delta_c = floor(4.148808e3 d (f_c^-2 - f_hi^-2) / (D tsamp) + 1/2)   (FP64),
+ *   out[j] = sum_c y_c[j + delta_c],   y_c read as D m_c past its end,
+ *   m_c = floor((sum_t x[t][c] + nsamp/2) / nsamp)  (the channel's rounded mean),
+ * with f_c = f0 + c df (MHz) and f_hi the highest channel frequency. All sums
+ * are integers below 2^24 (nchan D 255 < 2^24 is required), exact in float32.
+ */
+typedef struct {
+    double  dm_start;   /* pc cm^-3, >= 0 */
+    double  dm_step;    /* >= 0 */
+    int32_t ndm;        /* trial DMs dm_start + i dm_step, i < ndm */
+    int32_t downsamp;   /* D >= 1, dividing nsamp */
+} fdas_dm_range;
+
+/* Dedisperse fil_dev (device uint8 [nsamp][nchan], time-major as filterbank
+ * files store it) for every range. out_dev (device float32) receives, range
+ * after range, [ndm][nsamp / D] series, so that it is directly a packed batch
+ * for fdas_search_ragged (series i of range r at offset
+ * sum_{r' < r} ndm_r' nsamp / D_r' + i nsamp / D_r, sampled every D_r tsamp).
+ * out_elems: capacity of out_dev in floats. Uses the plan's stream handling
+ * and workspace (grown as needed); the plan's series limits do not apply. */
+fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, int32_t nchan, double tsamp,
+                            double f0_mhz, double df_mhz, const fdas_dm_range *ranges, int32_t nranges,
+                            float *out_dev, int64_t out_elems, void *stream);
+
 /* ------------------------------------------------------------------ refinement
  *
  * Refinement maximises the correlation power of a candidate over continuous
@@ -269,9 +299,9 @@ fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out);
  * launches of phase i since the last reset (both arrays hold FDAS_NPHASES
  * entries, either may be NULL). Phases: 0 real FFT, 1 normalisation,
  * 2 power plane, 3 harmonic sums, 4 compaction, 5 drift argmax, 6 copy-out,
- * 7 refinement.
+ * 7 refinement, 8 dedispersion.
  * reset != 0 clears the totals after reading. */
-#define FDAS_NPHASES 8
+#define FDAS_NPHASES 9
 fdas_status fdas_profile_read(fdas_plan p, double *ms, int64_t *launches, int32_t reset);
 
 /* Description of a status code (static storage). */

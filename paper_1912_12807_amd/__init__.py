@@ -27,9 +27,9 @@ EXPORTED = (
     "fdas_harmsum", "fdas_spectrum", "fdas_geometry", "fdas_threshold", "fdas_sigma",
     "fdas_template_taps", "fdas_status_string", "fdas_last_error", "fdas_profile_read",
     "fdas_plan_get_info", "fdas_search_ragged", "fdas_tuning_export", "fdas_tuning_import",
-    "fdas_refine_eval", "fdas_refine_grad", "fdas_refine", "fdas_refine_window",
+    "fdas_refine_eval", "fdas_refine_grad", "fdas_refine", "fdas_refine_window", "fdas_dedisperse",
 )
-PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "argmax", "copyout", "refine")
+PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "argmax", "copyout", "refine", "dedisperse")
 
 
 class PlanOpts(ctypes.Structure):
@@ -52,6 +52,8 @@ CAND_DTYPE = np.dtype([("series", "<i4"), ("harm", "<i4"), ("r_idx", "<i8"), ("z
                        ("power", "<f4"), ("sigma", "<f8"), ("r_fund", "<f8"), ("z_fund", "<f8"),
                        ("f_hz", "<f8"), ("fdot_hz_s", "<f8")], align=True)
 assert CAND_DTYPE.itemsize == 64
+DM_RANGE_DTYPE = np.dtype([("dm_start", "<f8"), ("dm_step", "<f8"), ("ndm", "<i4"), ("downsamp", "<i4")])
+assert DM_RANGE_DTYPE.itemsize == 24
 REFINE_DTYPE = np.dtype([("series", "<i4"), ("m", "<i4"), ("k0", "<i8"), ("r", "<f8"), ("z", "<f8")])
 assert REFINE_DTYPE.itemsize == 32
 
@@ -132,6 +134,9 @@ def load(path: Optional[str] = None):
     lib.fdas_refine_window.argtypes = [c.c_double, c.c_double, c.c_double, c.c_int32, c.POINTER(c.c_int64),
                                        c.POINTER(c.c_int32)]
     lib.fdas_refine_window.restype = c.c_int
+    lib.fdas_dedisperse.argtypes = [P, P, c.c_int64, c.c_int32, c.c_double, c.c_double, c.c_double, P, c.c_int32,
+                                    P, c.c_int64, P]
+    lib.fdas_dedisperse.restype = c.c_int
     _lib = lib
     return lib
 
@@ -266,6 +271,31 @@ class Plan:
         st = self.lib.fdas_tuning_import(self.handle, text.encode())
         if st != FDAS_OK:
             self._raise(st, "fdas_tuning_import")
+
+    def dedisperse(self, fil, tsamp: float, f0_mhz: float, df_mhz: float, ranges, stream=None):
+        """Dedisperse a CUDA uint8 [nsamp][nchan] filterbank for DM plan ranges
+        (dm_start, dm_step, ndm, downsamp). Returns (buf, series): buf is the packed
+        CUDA float32 output, series a list of per-range [ndm][nsamp/D] views of it."""
+        import torch
+        if not (isinstance(fil, torch.Tensor) and fil.is_cuda and fil.dtype == torch.uint8 and fil.dim() == 2
+                and fil.is_contiguous()):
+            raise TypeError("fil must be a contiguous CUDA uint8 [nsamp][nchan] tensor")
+        rg = np.zeros(len(ranges), dtype=DM_RANGE_DTYPE)
+        for i, (a, s_, n, d) in enumerate(ranges):
+            rg[i] = (a, s_, n, d)
+        nsamp, nchan = fil.shape
+        sizes = [int(n) * (nsamp // int(d)) if int(d) > 0 else 0 for _, _, n, d in ranges]
+        buf = torch.empty(max(1, sum(sizes)), dtype=torch.float32, device=fil.device)
+        st = self.lib.fdas_dedisperse(self.handle, ctypes.c_void_p(fil.data_ptr()), nsamp, nchan, float(tsamp),
+                                      float(f0_mhz), float(df_mhz), rg.ctypes.data_as(ctypes.c_void_p), len(rg),
+                                      ctypes.c_void_p(buf.data_ptr()), buf.numel(), _stream_handle(stream))
+        if st != FDAS_OK:
+            self._raise(st, "fdas_dedisperse")
+        out, o = [], 0
+        for (_, _, n, d), sz in zip(ranges, sizes):
+            out.append(buf[o:o + sz].view(int(n), nsamp // int(d)))
+            o += sz
+        return buf, out
 
     def refine(self, t, r0, z0, series=None, dz: float = None, iters: int = 20, stream=None):
         """Refine start points (r0, z0) [bins] of series ``series`` of the CUDA float32

@@ -14,6 +14,7 @@
 #include "fdas_internal.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -161,6 +162,14 @@ struct fdas_plan_s {
     DevCand *h_rec = nullptr;
     int64_t h_rec_cap = 0;
     int64_t *h_offs = nullptr;
+    // dedispersion: boxcar rows of two ranges, delay tables
+    float *d_dd[2] = {nullptr, nullptr};
+    int64_t dd_cap = 0;                 // floats per buffer
+    int32_t *d_delays = nullptr, *h_delays = nullptr;
+    int64_t delays_cap = 0;
+    unsigned long long *d_csum = nullptr;   // per-channel sums and rounded means
+    float *d_cpad = nullptr;
+    int32_t cpad_cap = 0;
     // refinement points
     fdas_refine_point *d_rpts = nullptr, *h_rpts = nullptr;
     float *d_rpow = nullptr, *h_rpow = nullptr;
@@ -835,7 +844,7 @@ void fdas_plan_destroy(fdas_plan p) {
     for (auto &b : p->banks) (void)hipFree(b.d);
     for (auto &t : p->tables) (void)hipFree(t.d);
     void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_med, p->d_thr, p->d_state, p->d_offs,
-                   p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow};
+                   p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow, p->d_dd[0], p->d_dd[1], p->d_delays, p->d_csum, p->d_cpad};
     for (void *q : dev)
         if (q) (void)hipFree(q);
     for (auto &t : p->ev_pending) {
@@ -843,7 +852,7 @@ void fdas_plan_destroy(fdas_plan p) {
         p->ev_pool.push_back(std::get<2>(t));
     }
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-    void *host[] = {p->h_state, p->h_small, p->h_rec, p->h_offs, p->h_rpts, p->h_rpow};
+    void *host[] = {p->h_state, p->h_small, p->h_rec, p->h_offs, p->h_rpts, p->h_rpow, p->h_delays};
     for (void *q : host)
         if (q) (void)hipHostFree(q);
     if (cur >= 0) (void)hipSetDevice(cur);
@@ -1037,6 +1046,118 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
         << p->rec_cap;
     for (const auto &G : B.groups) key_group(key, G);
     return run_batch(p, series_dev, true, B, dz, numharm, key.str(), out_host, cap, n_total, st);
+}
+
+fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, int32_t nchan, double tsamp,
+                            double f0_mhz, double df_mhz, const fdas_dm_range *ranges, int32_t nranges,
+                            float *out_dev, int64_t out_elems, void *stream) {
+    TRY(check_plan(p));
+    if (!fil_dev || !out_dev || ((uintptr_t)out_dev & 3) || !ranges || nranges < 1 || nsamp < 1 || nchan < 1 ||
+        nchan > 65535 || !(tsamp > 0) || !std::isfinite(tsamp) || !std::isfinite(f0_mhz) || !std::isfinite(df_mhz))
+        return p->fail(FDAS_E_INVAL, "bad filterbank description or buffers");
+    const double flast = f0_mhz + (nchan - 1) * df_mhz;
+    if (!(f0_mhz > 0) || !(flast > 0)) return p->fail(FDAS_E_INVAL, "channel frequencies must be positive");
+    const double fhi = std::max(f0_mhz, flast);
+    int64_t need = 0, ndel = 0, rows_max = 0;
+    for (int r = 0; r < nranges; ++r) {
+        const fdas_dm_range &R = ranges[r];
+        if (R.ndm < 1 || R.downsamp < 1 || nsamp % R.downsamp || !(R.dm_start >= 0) || !(R.dm_step >= 0) ||
+            !std::isfinite(R.dm_start) || !std::isfinite(R.dm_step))
+            return p->fail(FDAS_E_INVAL, "DM range: ndm >= 1, downsamp >= 1 dividing nsamp, DMs >= 0");
+        if ((double)nchan * R.downsamp * 255.0 >= 16777216.0 || nsamp > (int64_t)65535 * 4096)
+            return p->fail(FDAS_E_UNSUPPORTED, "sums beyond 2^24 (nchan D 255) or more than 2^28 samples");
+        need += (int64_t)R.ndm * (nsamp / R.downsamp);
+        ndel += (int64_t)R.ndm * nchan;
+        rows_max = std::max<int64_t>(rows_max, nsamp / R.downsamp);
+    }
+    if (need > out_elems) return p->fail(FDAS_E_INVAL, "output buffer too small for the DM plan");
+    // delays, FP64, in the order of the formula: K DM (f^-2 - fhi^-2) / (D tsamp) + 1/2, floor
+    if (ndel > p->delays_cap) {
+        TRY(dalloc(p, &p->d_delays, ndel, "delay tables"));
+        TRY(halloc(p, &p->h_delays, ndel, "delay tables"));
+        p->delays_cap = ndel;
+    }
+    std::vector<int> group(nranges), span(nranges);
+    {
+        int64_t o = 0;
+        for (int r = 0; r < nranges; ++r) {
+            const fdas_dm_range &R = ranges[r];
+            for (int i = 0; i < R.ndm; ++i) {
+                const double dm = R.dm_start + i * R.dm_step;
+                for (int c = 0; c < nchan; ++c) {
+                    const double f = f0_mhz + c * df_mhz;
+                    const double x = 4.148808e3 * dm * (1.0 / (f * f) - 1.0 / (fhi * fhi)) /
+                                     ((double)R.downsamp * tsamp) + 0.5;
+                    const double d = std::floor(x);
+                    if (!(d <= 2e9)) return p->fail(FDAS_E_INVAL, "dispersion delay beyond 2^31 samples");
+                    p->h_delays[o + (int64_t)i * nchan + c] = (int32_t)d;
+                }
+            }
+            // the widest group of trial DMs whose delay spreads fit the LDS stage
+            const int32_t *dl = p->h_delays + o;
+            for (int G = 16; G >= 1; G /= 2) {
+                int sp = 0;
+                for (int i0 = 0; i0 < R.ndm; i0 += G)
+                    for (int c = 0; c < nchan; ++c) {
+                        int lo = INT32_MAX, hi = INT32_MIN;
+                        for (int g = 0; g < G; ++g) {
+                            const int v = dl[(int64_t)std::min(i0 + g, R.ndm - 1) * nchan + c];
+                            lo = std::min(lo, v);
+                            hi = std::max(hi, v);
+                        }
+                        sp = std::max(sp, hi - lo);
+                    }
+                if (dedisperse_lds_bytes(sp) <= 64 * 1024 || G == 1) {
+                    group[r] = G;
+                    span[r] = sp;
+                    break;
+                }
+            }
+            o += (int64_t)R.ndm * nchan;
+        }
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (rows_max * nchan > p->dd_cap) {
+        TRY(dalloc(p, &p->d_dd[0], rows_max * nchan, "dedispersion rows"));
+        TRY(dalloc(p, &p->d_dd[1], rows_max * nchan, "dedispersion rows"));
+        p->dd_cap = rows_max * nchan;
+    }
+    if (nchan > p->cpad_cap) {
+        TRY(dalloc(p, &p->d_csum, nchan, "channel sums"));
+        TRY(dalloc(p, &p->d_cpad, nchan, "channel means"));
+        p->cpad_cap = nchan;
+    }
+    HIPTRY(p, hipMemcpyAsync(p->d_delays, p->h_delays, ndel * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    hipEvent_t e = p->begin(st);
+    HIPTRY(p, launch_channel_pad(fil_dev, nsamp, nchan, p->d_csum, p->d_cpad, st));
+    // boxcar rows of a range come from the previous range's rows when its factor
+    // divides this one (the same rows when equal), otherwise from the file
+    int64_t o_out = 0, o_del = 0;
+    int ybuf = -1, prevD = 0;
+    for (int r = 0; r < nranges; ++r) {
+        const fdas_dm_range &R = ranges[r];
+        const int64_t n = nsamp / R.downsamp;
+        int nb = ybuf;
+        if (prevD != R.downsamp) {
+            nb = ybuf < 0 ? 0 : (ybuf ^ 1);
+            if (prevD && R.downsamp % prevD == 0) {
+                HIPTRY(p, launch_downsample_rows(p->d_dd[ybuf], nsamp / prevD, n, R.downsamp / prevD, nchan,
+                                                 p->d_dd[nb], n, st));
+            } else {
+                HIPTRY(p, launch_fil_downsample(fil_dev, nsamp, nchan, R.downsamp, p->d_dd[nb], n, st));
+            }
+        }
+        HIPTRY(p, launch_dedisperse(p->d_dd[nb], n, n, nchan, p->d_cpad, R.downsamp, p->d_delays + o_del, R.ndm,
+                                    group[r], span[r], out_dev + o_out, n, st));
+        o_out += (int64_t)R.ndm * n;
+        o_del += (int64_t)R.ndm * nchan;
+        ybuf = nb;
+        prevD = R.downsamp;
+    }
+    p->end(8, e, st);
+    HIPTRY(p, hipStreamSynchronize(st));
+    p->collect();
+    return FDAS_OK;
 }
 
 fdas_status fdas_refine_window(double r0, double z0, double dz, int32_t K, int64_t *k0, int32_t *m) {
