@@ -251,8 +251,8 @@ class Plan:
                                          float(dz), int(numharm), float(sigma),
                                          out.ctypes.data_as(ctypes.c_void_p), int(cap), ctypes.byref(n),
                                          _stream_handle(stream))
-        if st == FDAS_E_TRUNC and allow_trunc:
-            return out[:cap], int(n.value)
+        if allow_trunc and st in (FDAS_OK, FDAS_E_TRUNC):
+            return out[:min(int(cap), int(n.value))].copy(), int(n.value)
         if st != FDAS_OK:
             self._raise(st, "fdas_search_ragged")
         return out[:n.value].copy()

@@ -167,6 +167,9 @@ struct fdas_plan_s {
     int64_t dd_cap = 0;                 // floats per buffer
     int32_t *d_delays = nullptr, *h_delays = nullptr;
     int64_t delays_cap = 0;
+    std::string dd_key;                     // description of the plan whose delay tables are on the device
+    std::vector<int> dd_group, dd_span, dd_npad;
+    int64_t dd_ntab = 0;
     unsigned long long *d_csum = nullptr;   // per-channel sums and rounded means
     float *d_cpad = nullptr;
     int32_t cpad_cap = 0;
@@ -1058,7 +1061,7 @@ fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, 
     const double flast = f0_mhz + (nchan - 1) * df_mhz;
     if (!(f0_mhz > 0) || !(flast > 0)) return p->fail(FDAS_E_INVAL, "channel frequencies must be positive");
     const double fhi = std::max(f0_mhz, flast);
-    int64_t need = 0, ndel = 0, rows_max = 0;
+    int64_t need = 0, rows_max = 0;
     for (int r = 0; r < nranges; ++r) {
         const fdas_dm_range &R = ranges[r];
         if (R.ndm < 1 || R.downsamp < 1 || nsamp % R.downsamp || !(R.dm_start >= 0) || !(R.dm_step >= 0) ||
@@ -1067,55 +1070,81 @@ fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, 
         if ((double)nchan * R.downsamp * 255.0 >= 16777216.0 || nsamp > (int64_t)65535 * 4096)
             return p->fail(FDAS_E_UNSUPPORTED, "sums beyond 2^24 (nchan D 255) or more than 2^28 samples");
         need += (int64_t)R.ndm * (nsamp / R.downsamp);
-        ndel += (int64_t)R.ndm * nchan;
         rows_max = std::max<int64_t>(rows_max, nsamp / R.downsamp);
     }
     if (need > out_elems) return p->fail(FDAS_E_INVAL, "output buffer too small for the DM plan");
-    // delays, FP64, in the order of the formula: K DM (f^-2 - fhi^-2) / (D tsamp) + 1/2, floor
-    if (ndel > p->delays_cap) {
-        TRY(dalloc(p, &p->d_delays, ndel, "delay tables"));
-        TRY(halloc(p, &p->h_delays, ndel, "delay tables"));
-        p->delays_cap = ndel;
-    }
-    std::vector<int> group(nranges), span(nranges);
+    // delay tables depend only on the description: keep them on the device between calls
+    std::string key;
     {
-        int64_t o = 0;
+        std::ostringstream k;
+        k.precision(17);
+        k << nsamp << ' ' << nchan << ' ' << tsamp << ' ' << f0_mhz << ' ' << df_mhz;
+        for (int r = 0; r < nranges; ++r)
+            k << '|' << ranges[r].dm_start << ',' << ranges[r].dm_step << ',' << ranges[r].ndm << ','
+              << ranges[r].downsamp;
+        key = k.str();
+    }
+    const bool have_tables = (key == p->dd_key);
+    if (!have_tables) {
+        p->dd_key.clear();
+        // delays, FP64, in the order of the formula: K DM (f^-2 - fhi^-2) / (D tsamp) + 1/2, floor;
+        // per range a table [nchan][ndm_pad] (ndm_pad a multiple of the DM group, entries
+        // past ndm repeating the last DM) and the group size / staged channels that fit LDS
+        std::vector<int> group(nranges), span(nranges), npad(nranges);
+        std::vector<std::vector<int32_t>> tab(nranges);
+        int64_t ntab = 0;
         for (int r = 0; r < nranges; ++r) {
             const fdas_dm_range &R = ranges[r];
+            std::vector<int32_t> d((size_t)R.ndm * nchan);      // [dm][c]
             for (int i = 0; i < R.ndm; ++i) {
                 const double dm = R.dm_start + i * R.dm_step;
                 for (int c = 0; c < nchan; ++c) {
                     const double f = f0_mhz + c * df_mhz;
-                    const double x = 4.148808e3 * dm * (1.0 / (f * f) - 1.0 / (fhi * fhi)) /
-                                     ((double)R.downsamp * tsamp) + 0.5;
-                    const double d = std::floor(x);
-                    if (!(d <= 2e9)) return p->fail(FDAS_E_INVAL, "dispersion delay beyond 2^31 samples");
-                    p->h_delays[o + (int64_t)i * nchan + c] = (int32_t)d;
+                    const double x =
+                        4.148808e3 * dm * (1.0 / (f * f) - 1.0 / (fhi * fhi)) / ((double)R.downsamp * tsamp) + 0.5;
+                    const double v = std::floor(x);
+                    if (!(v <= 2e9)) return p->fail(FDAS_E_INVAL, "dispersion delay beyond 2^31 samples");
+                    d[(size_t)i * nchan + c] = (int32_t)v;
                 }
             }
-            // the widest group of trial DMs whose delay spreads fit the LDS stage
-            const int32_t *dl = p->h_delays + o;
             for (int G = 16; G >= 1; G /= 2) {
                 int sp = 0;
                 for (int i0 = 0; i0 < R.ndm; i0 += G)
-                    for (int c = 0; c < nchan; ++c) {
-                        int lo = INT32_MAX, hi = INT32_MIN;
-                        for (int g = 0; g < G; ++g) {
-                            const int v = dl[(int64_t)std::min(i0 + g, R.ndm - 1) * nchan + c];
-                            lo = std::min(lo, v);
-                            hi = std::max(hi, v);
-                        }
-                        sp = std::max(sp, hi - lo);
-                    }
-                if (dedisperse_lds_bytes(sp) <= 64 * 1024 || G == 1) {
+                    for (int c = 0; c < nchan; ++c)
+                        sp = std::max(sp, d[(size_t)std::min(i0 + G - 1, R.ndm - 1) * nchan + c] -
+                                              d[(size_t)i0 * nchan + c]);
+                if (dedisperse_width(sp) || G == 1) {
                     group[r] = G;
                     span[r] = sp;
                     break;
                 }
             }
-            o += (int64_t)R.ndm * nchan;
+            const int G = group[r];
+            npad[r] = (R.ndm + G - 1) / G * G;
+            tab[r].resize((size_t)nchan * npad[r]);
+            for (int c = 0; c < nchan; ++c)
+                for (int i = 0; i < npad[r]; ++i)
+                    tab[r][(size_t)c * npad[r] + i] = d[(size_t)std::min(i, R.ndm - 1) * nchan + c];
+            ntab += (int64_t)nchan * npad[r];
         }
+        if (ntab > p->delays_cap) {
+            TRY(dalloc(p, &p->d_delays, ntab, "delay tables"));
+            TRY(halloc(p, &p->h_delays, ntab, "delay tables"));
+            p->delays_cap = ntab;
+        }
+        {
+            int64_t o = 0;
+            for (int r = 0; r < nranges; ++r) {
+                std::memcpy(p->h_delays + o, tab[r].data(), tab[r].size() * sizeof(int32_t));
+                o += (int64_t)tab[r].size();
+            }
+        }
+        p->dd_group = group;
+        p->dd_span = span;
+        p->dd_npad = npad;
+        p->dd_ntab = ntab;
     }
+    const std::vector<int> &group = p->dd_group, &span = p->dd_span, &npad = p->dd_npad;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (rows_max * nchan > p->dd_cap) {
         TRY(dalloc(p, &p->d_dd[0], rows_max * nchan, "dedispersion rows"));
@@ -1127,11 +1156,16 @@ fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, 
         TRY(dalloc(p, &p->d_cpad, nchan, "channel means"));
         p->cpad_cap = nchan;
     }
-    HIPTRY(p, hipMemcpyAsync(p->d_delays, p->h_delays, ndel * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (!have_tables) {
+        HIPTRY(p, hipMemcpyAsync(p->d_delays, p->h_delays, p->dd_ntab * sizeof(int32_t), hipMemcpyHostToDevice,
+                                 st));
+        p->dd_key = key;
+    }
     hipEvent_t e = p->begin(st);
-    HIPTRY(p, launch_channel_pad(fil_dev, nsamp, nchan, p->d_csum, p->d_cpad, st));
+    HIPTRY(p, launch_zero_sums(p->d_csum, nchan, st));
     // boxcar rows of a range come from the previous range's rows when its factor
-    // divides this one (the same rows when equal), otherwise from the file
+    // divides this one (the same rows when equal), otherwise from the file; the
+    // first pass over the file also totals each channel for the padding mean
     int64_t o_out = 0, o_del = 0;
     int ybuf = -1, prevD = 0;
     for (int r = 0; r < nranges; ++r) {
@@ -1144,13 +1178,15 @@ fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, 
                 HIPTRY(p, launch_downsample_rows(p->d_dd[ybuf], nsamp / prevD, n, R.downsamp / prevD, nchan,
                                                  p->d_dd[nb], n, st));
             } else {
-                HIPTRY(p, launch_fil_downsample(fil_dev, nsamp, nchan, R.downsamp, p->d_dd[nb], n, st));
+                HIPTRY(p, launch_fil_downsample(fil_dev, nsamp, nchan, R.downsamp, p->d_dd[nb], n,
+                                                ybuf < 0 ? p->d_csum : nullptr, st));
             }
         }
+        if (r == 0) HIPTRY(p, launch_channel_pad(p->d_csum, nsamp, nchan, p->d_cpad, st));
         HIPTRY(p, launch_dedisperse(p->d_dd[nb], n, n, nchan, p->d_cpad, R.downsamp, p->d_delays + o_del, R.ndm,
-                                    group[r], span[r], out_dev + o_out, n, st));
+                                    npad[r], group[r], span[r], out_dev + o_out, n, st));
         o_out += (int64_t)R.ndm * n;
-        o_del += (int64_t)R.ndm * nchan;
+        o_del += (int64_t)nchan * npad[r];
         ybuf = nb;
         prevD = R.downsamp;
     }

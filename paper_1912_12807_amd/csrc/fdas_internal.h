@@ -148,29 +148,34 @@ hipError_t launch_argmax(const float *plane, int64_t pitch, int64_t series_strid
                          int Z, int numharm, int b0, DevCand *rec, const int64_t *state,
                          int64_t cap, hipStream_t st);
 
+// K0: dedispersion. x: time-major uint8 [nsamp][nchan]; y: channel-major float
+// rows [nchan][ypitch] of boxcar sums over D samples (n = nsamp / D outputs).
+// With sums set (zeroed by launch_zero_sums), the channels' sample totals are
+// added to sums[c].
+hipError_t launch_fil_downsample(const uint8_t *x, int64_t nsamp, int nchan, int D, float *y, int64_t ypitch,
+                                 unsigned long long *sums, hipStream_t st);
+hipError_t launch_zero_sums(unsigned long long *sums, int nchan, hipStream_t st);
+// pad[c] = floor((sums[c] + nsamp/2) / nsamp).
+hipError_t launch_channel_pad(const unsigned long long *sums, int64_t nsamp, int nchan, float *pad, hipStream_t st);
+// out[c][j] = sum_{k<f} in[c][j f + k] for j < n_out, c < nchan.
+hipError_t launch_downsample_rows(const float *in, int64_t ipitch, int64_t n_out, int f, int nchan, float *out,
+                                  int64_t opitch, hipStream_t st);
+// LDS row width (floats) that launch_dedisperse stages for a delay spread
+// span_max (0 if the spread is too wide for groups of more than one trial).
+int dedisperse_width(int span_max);
+// out[i][j] = sum_c y[c][j + delays[c][i]] (D pad[c] past n - 1), groups of G trial
+// DMs per block (G in 1, 2, 4, 8, 16), 16 channels per LDS stage. delays:
+// [nchan][ndm_pad], non-decreasing in i, ndm_pad a multiple of G with entries
+// past ndm repeating the last DM; span_max bounds delays[c][i0 + G - 1] -
+// delays[c][i0] over groups and channels.
+hipError_t launch_dedisperse(const float *y, int64_t ypitch, int64_t n, int nchan, const float *pad, int D,
+                             const int32_t *delays, int ndm, int ndm_pad, int G, int span_max, float *out,
+                             int64_t opitch, hipStream_t st);
+
 // K7/K8: refinement objective (see fdas_refine_eval), its gradients and the
 // ascent. One wave per point; the window of 2 m + 1 bins is staged in LDS, so
 // every point must have m <= max_m <= kRefineMaxM (others give NaN).
 constexpr int kRefineMaxM = 2000;
-
-// K0: dedispersion. x: time-major uint8 [nsamp][nchan]; y: channel-major float
-// rows [nchan][ypitch] of boxcar sums over D samples (n = nsamp / D outputs).
-hipError_t launch_fil_downsample(const uint8_t *x, int64_t nsamp, int nchan, int D, float *y, int64_t ypitch,
-                                 hipStream_t st);
-// pad[c] = floor((sum_t x[t][c] + nsamp/2) / nsamp) (sums: scratch of nchan uint64).
-hipError_t launch_channel_pad(const uint8_t *x, int64_t nsamp, int nchan, unsigned long long *sums, float *pad,
-                              hipStream_t st);
-// out[c][j] = sum_{k<f} in[c][j f + k] for j < n_out, c < nchan.
-hipError_t launch_downsample_rows(const float *in, int64_t ipitch, int64_t n_out, int f, int nchan, float *out,
-                                  int64_t opitch, hipStream_t st);
-// LDS that launch_dedisperse needs for a delay spread span_max (at most 64 KB).
-size_t dedisperse_lds_bytes(int span_max);
-// out[i][j] = sum_c y[c][j + delays[i][c]] (D pad[c] past n - 1; delays >= 0), groups of G trial DMs
-// per block (G in 1, 2, 4, 8, 16); span_max bounds max_g - min_g of the delays of
-// every group and channel, the last DM standing in for group members past ndm.
-hipError_t launch_dedisperse(const float *y, int64_t ypitch, int64_t n, int nchan, const float *pad, int D,
-                             const int32_t *delays, int ndm, int G, int span_max, float *out, int64_t opitch,
-                             hipStream_t st);
 hipError_t launch_refine_eval(const float2 *spec, int64_t spitch, int64_t nbins, int nseries, const float *scale,
                               const fdas_refine_point *pts, int64_t n, int max_m, float *power, float *dpdr,
                               float *dpdz, hipStream_t st);

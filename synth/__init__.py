@@ -319,8 +319,8 @@ class Filterbank:
 def fast_filterbank(nsamp: int = 1 << 18) -> Filterbank:
     """FAST drift-scan file shape (Table 1): 200 channels of 0.25 MHz over 290-340 MHz,
     0.2 ms sampling, 2^18 samples (52.4288 s), 8 bits; three dispersed pulsars."""
-    psr = [DispersedPulsar(0.08731, 12.3, 1.2, 0.05, 0.1), DispersedPulsar(0.31412, 45.6, 2.0, 0.03, 0.6),
-           DispersedPulsar(0.02573, 88.8, 1.0, 0.08, 0.3)]
+    psr = [DispersedPulsar(0.08731, 12.3, 0.3, 0.05, 0.1), DispersedPulsar(0.31412, 45.6, 0.5, 0.03, 0.6),
+           DispersedPulsar(0.02573, 88.8, 0.25, 0.08, 0.3)]
     return Filterbank("fast-filterbank-200x2^18", 200, nsamp, 2.0e-4, 290.125, 0.25, psr, DDPLAN_FAST,
                       seed_for(6, 0))
 
@@ -328,7 +328,7 @@ def fast_filterbank(nsamp: int = 1 << 18) -> Filterbank:
 def pmps_filterbank(nsamp: int = 1 << 23) -> Filterbank:
     """PMPS file shape (Table 1): 96 channels of 3 MHz over 1231.5-1516.5 MHz (descending),
     250 us sampling, 2^23 samples, 8 bits; two dispersed pulsars."""
-    psr = [DispersedPulsar(0.4471, 180.5, 1.5, 0.04, 0.2), DispersedPulsar(0.00412, 33.3, 0.6, 0.10, 0.7)]
+    psr = [DispersedPulsar(0.4471, 180.5, 0.1, 0.04, 0.2), DispersedPulsar(0.00412, 33.3, 0.04, 0.10, 0.7)]
     return Filterbank("pmps-filterbank-96x2^23", 96, nsamp, 2.5e-4, 1515.0, -3.0, psr, DDPLAN_PMPS,
                       seed_for(7, 0))
 
