@@ -21,3 +21,7 @@ from .dedisp_oracle import *  # noqa: F401,F403
 from .dedisp_oracle import __all__ as _dedisp_all  # noqa: F401
 
 __all__ = list(__all__) + list(_dedisp_all)
+from .sift_oracle import *  # noqa: F401,F403
+from .sift_oracle import __all__ as _sift_all  # noqa: F401
+
+__all__ = list(__all__) + list(_sift_all)
