@@ -49,7 +49,12 @@ typedef enum {
     FDAS_E_UNSUPPORTED = -5   /* valid but not supported (e.g. N not a power of two) */
 } fdas_status;
 
-typedef enum { FDAS_NORM_MEDIAN = 0, FDAS_NORM_FIXED = 1 } fdas_norm;
+/* FDAS_NORM_LOCAL (red-noise normalisation): bins 1..N/2-1 are cut into blocks
+ * starting at b_0 = 1 of width min(200, 6 + floor(b_i / 30)); each block's lower
+ * median power / ln 2 sits at the block centre, the mean-power estimate m(k)
+ * interpolates linearly between centres (constant outside them) and
+ * A^_k = A_k / sqrt(m(k)). fdas_spectrum then returns the normalised spectra. */
+typedef enum { FDAS_NORM_MEDIAN = 0, FDAS_NORM_FIXED = 1, FDAS_NORM_LOCAL = 2 } fdas_norm;
 
 typedef struct {
     double  flo_hz;              /* lowest searched frequency, Hz (default 1.0) */
@@ -152,6 +157,33 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
  * tuning file kept by the caller), replacing entries of the same shape. */
 fdas_status fdas_tuning_export(fdas_plan p, char *buf, int64_t cap, int64_t *len);
 fdas_status fdas_tuning_import(fdas_plan p, const char *text);
+
+/* ------------------------------------------------------------------ sifting
+ *
+ * Sifting of a candidate list (the paper's Section 2, step 5), on each
+ * candidate's fundamental frequency f_hz and significance sigma:
+ *   order: sigma descending, then series, harm, r_idx ascending;
+ *   duplicates: walking that order, a candidate within tol_bins / min(T_a, T_b)
+ *     Hz of an already kept candidate joins the first such kept candidate,
+ *     otherwise it is kept (T = r_fund / f_hz, the observation length);
+ *   harmonics: walking the kept candidates in order, B is dropped when a
+ *     stronger surviving A has |f_B - rho f_A| <= rho tol_bins / min(T_A, T_B)
+ *     for rho = n or 1/n, 2 <= n <= max_ratio.
+ * Host only; any mix of series (e.g. all trial DMs of one observation).
+ */
+typedef struct {
+    int64_t index;       /* surviving candidate: its position in the input list */
+    int32_t hits;        /* candidates it stands for (itself and its duplicates) */
+    int32_t series_lo;   /* smallest and largest series index among them */
+    int32_t series_hi;
+    int32_t reserved;
+} fdas_sifted;
+
+/* Survivors in sifted order into out (cap entries; *n_out = their number,
+ * FDAS_E_TRUNC when cap is smaller). Every candidate needs f_hz > 0, r_fund > 0
+ * and a finite sigma (FDAS_E_INVAL otherwise). */
+fdas_status fdas_sift(const fdas_cand *cands, int64_t n, double tol_bins, int32_t max_ratio,
+                      fdas_sifted *out, int64_t cap, int64_t *n_out);
 
 /* ------------------------------------------------------------------ dedispersion
  *

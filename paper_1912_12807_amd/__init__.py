@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdas.so")
 
 FDAS_OK, FDAS_E_INVAL, FDAS_E_NOMEM, FDAS_E_DEVICE, FDAS_E_TRUNC, FDAS_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-NORM_MEDIAN, NORM_FIXED = 0, 1
+NORM_MEDIAN, NORM_FIXED, NORM_LOCAL = 0, 1, 2
 
 EXPORTED = (
     "fdas_plan_opts_default", "fdas_plan_create", "fdas_plan_destroy", "fdas_search", "fdas_plane",
@@ -28,6 +28,7 @@ EXPORTED = (
     "fdas_template_taps", "fdas_status_string", "fdas_last_error", "fdas_profile_read",
     "fdas_plan_get_info", "fdas_search_ragged", "fdas_tuning_export", "fdas_tuning_import",
     "fdas_refine_eval", "fdas_refine_grad", "fdas_refine", "fdas_refine_window", "fdas_dedisperse",
+    "fdas_sift",
 )
 PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "argmax", "copyout", "refine", "dedisperse")
 
@@ -52,6 +53,9 @@ CAND_DTYPE = np.dtype([("series", "<i4"), ("harm", "<i4"), ("r_idx", "<i8"), ("z
                        ("power", "<f4"), ("sigma", "<f8"), ("r_fund", "<f8"), ("z_fund", "<f8"),
                        ("f_hz", "<f8"), ("fdot_hz_s", "<f8")], align=True)
 assert CAND_DTYPE.itemsize == 64
+SIFTED_DTYPE = np.dtype([("index", "<i8"), ("hits", "<i4"), ("series_lo", "<i4"), ("series_hi", "<i4"),
+                         ("reserved", "<i4")])
+assert SIFTED_DTYPE.itemsize == 24
 DM_RANGE_DTYPE = np.dtype([("dm_start", "<f8"), ("dm_step", "<f8"), ("ndm", "<i4"), ("downsamp", "<i4")])
 assert DM_RANGE_DTYPE.itemsize == 24
 REFINE_DTYPE = np.dtype([("series", "<i4"), ("m", "<i4"), ("k0", "<i8"), ("r", "<f8"), ("z", "<f8")])
@@ -137,6 +141,8 @@ def load(path: Optional[str] = None):
     lib.fdas_dedisperse.argtypes = [P, P, c.c_int64, c.c_int32, c.c_double, c.c_double, c.c_double, P, c.c_int32,
                                     P, c.c_int64, P]
     lib.fdas_dedisperse.restype = c.c_int
+    lib.fdas_sift.argtypes = [P, c.c_int64, c.c_double, c.c_int32, P, c.c_int64, c.POINTER(c.c_int64)]
+    lib.fdas_sift.restype = c.c_int
     _lib = lib
     return lib
 
@@ -146,7 +152,7 @@ def default_opts(**kw) -> PlanOpts:
     load().fdas_plan_opts_default(ctypes.byref(o))
     for k, v in kw.items():
         if k == "norm" and isinstance(v, str):
-            v = {"median": NORM_MEDIAN, "fixed": NORM_FIXED}[v]
+            v = {"median": NORM_MEDIAN, "fixed": NORM_FIXED, "local": NORM_LOCAL}[v]
         setattr(o, k, v)
     return o
 
@@ -507,3 +513,18 @@ def refine_power(spec, r, z, series, k0, m, max_m: int = None):
     if max_m is None:
         max_m = int(m.max().item()) if m.numel() else 0
     return _REFINE_FN.apply(torch.view_as_real(spec.contiguous()), r, z, series, k0, m, max_m)
+
+
+def sift(cands, tol_bins: float = 1.1, max_ratio: int = 16):
+    """Sift a candidate list (CAND_DTYPE array): duplicates by fundamental frequency,
+    then integer harmonics of stronger survivors. Returns SIFTED_DTYPE records
+    (index into cands, hits, series range) in sifted order (host only)."""
+    lib = load()
+    cands = np.ascontiguousarray(cands, dtype=CAND_DTYPE)
+    out = np.zeros(max(1, len(cands)), dtype=SIFTED_DTYPE)
+    n = ctypes.c_int64(0)
+    st = lib.fdas_sift(cands.ctypes.data_as(ctypes.c_void_p), len(cands), float(tol_bins), int(max_ratio),
+                       out.ctypes.data_as(ctypes.c_void_p), len(out), ctypes.byref(n))
+    if st != FDAS_OK:
+        raise FdasError(st, f"fdas_sift: {lib.fdas_status_string(st).decode()}")
+    return out[:n.value].copy()

@@ -170,6 +170,10 @@ struct fdas_plan_s {
     std::string dd_key;                     // description of the plan whose delay tables are on the device
     std::vector<int> dd_group, dd_span, dd_npad;
     int64_t dd_ntab = 0;
+    // local normalisation: block tables per half-length and block-median scratch
+    std::vector<std::pair<int64_t, std::pair<int32_t *, int>>> ltabs;
+    float *d_lmed = nullptr;
+    int64_t lmed_cap = 0;
     unsigned long long *d_csum = nullptr;   // per-channel sums and rounded means
     float *d_cpad = nullptr;
     int32_t cpad_cap = 0;
@@ -418,6 +422,42 @@ CorrGeom corr_geom(const Bank &bk, const Geometry &g) {
     return c;
 }
 
+// Block table of the local normalisation for spectra of `half` bins (cached), and
+// block-median scratch for nb series. Allocates only outside graph capture.
+fdas_status get_local(fdas_plan p, int64_t half, int nb, const int32_t **table, int *nblk) {
+    for (auto &t : p->ltabs)
+        if (t.first == half) {
+            *table = t.second.first;
+            *nblk = t.second.second;
+            break;
+        }
+    if (!*table) {
+        std::vector<int32_t> bs;
+        for (int64_t b = 1; b < half;) {
+            const int64_t e = std::min<int64_t>(half, b + std::min<int64_t>(200, 6 + b / 30));
+            bs.push_back((int32_t)b);
+            b = e;
+        }
+        bs.push_back((int32_t)half);
+        int32_t *d = nullptr;
+        TRY(dalloc(p, &d, (int64_t)bs.size(), "local-normalisation blocks"));
+        if (hipMemcpy(d, bs.data(), bs.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+            const hipError_t e = hipGetLastError();
+            (void)hipFree(d);
+            return p->hip(e == hipSuccess ? hipErrorUnknown : e, "local-normalisation block upload");
+        }
+        p->ltabs.push_back({half, {d, (int)bs.size() - 1}});
+        *table = d;
+        *nblk = (int)bs.size() - 1;
+    }
+    if ((int64_t)*nblk * nb > p->lmed_cap) {
+        TRY(dalloc(p, &p->d_lmed, (int64_t)*nblk * nb, "block medians"));
+        p->lmed_cap = (int64_t)*nblk * nb;
+        drop_graph(p);
+    }
+    return FDAS_OK;
+}
+
 // ---------------------------------------------------------------- enqueue helpers
 
 // K1 + K2 for nb series of nsamp samples (series b at x + b nsamp, or at
@@ -432,6 +472,13 @@ fdas_status run_spectrum(fdas_plan p, const float *x, const int64_t *offs, int64
         e = p->begin(st);
         HIPTRY(p, launch_median_scale(spec, p->spitch, nsamp / 2, nb, p->d_scale + v0, p->d_norm + v0, p->d_med,
                                       st));
+        p->end(1, e, st);
+    } else if (p->opts.norm == FDAS_NORM_LOCAL) {
+        const int32_t *tab = nullptr;
+        int nblk = 0;
+        TRY(get_local(p, nsamp / 2, nb, &tab, &nblk));
+        e = p->begin(st);
+        HIPTRY(p, launch_local_norm(spec, p->spitch, nsamp / 2, nb, tab, nblk, p->d_lmed, p->d_scale + v0, st));
         p->end(1, e, st);
     } else {
         const float sc = (float)std::sqrt(1.0 / ((double)nsamp * p->opts.fixed_var));
@@ -713,6 +760,18 @@ fdas_status run_batch(fdas_plan p, const float *x, bool ragged, const Batch &B, 
                 drop_graph(p);
                 if (!p->cap_st) HIPTRY(p, hipStreamCreateWithFlags(&p->cap_st, hipStreamNonBlocking));
                 // every bank and table of the batch must exist before capture
+                if (p->opts.norm == FDAS_NORM_LOCAL) {
+                    for (size_t i = 0; i < B.groups.size();) {
+                        size_t j = i;
+                        int nb = 0;
+                        while (j < B.groups.size() && B.groups[j].g.nsamp == B.groups[i].g.nsamp)
+                            nb += B.groups[j++].nb;
+                        const int32_t *tab = nullptr;
+                        int nblk = 0;
+                        TRY(get_local(p, B.groups[i].g.nsamp / 2, nb, &tab, &nblk));
+                        i = j;
+                    }
+                }
                 for (const auto &G : B.groups) {
                     const Bank *bk = nullptr;
                     TRY(get_bank(p, G.zmax, dz, G.cfg.L, &bk));
@@ -846,8 +905,9 @@ void fdas_plan_destroy(fdas_plan p) {
     if (p->cap_st) (void)hipStreamDestroy(p->cap_st);
     for (auto &b : p->banks) (void)hipFree(b.d);
     for (auto &t : p->tables) (void)hipFree(t.d);
+    for (auto &t : p->ltabs) (void)hipFree(t.second.first);
     void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_med, p->d_thr, p->d_state, p->d_offs,
-                   p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow, p->d_dd[0], p->d_dd[1], p->d_delays, p->d_csum, p->d_cpad};
+                   p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow, p->d_dd[0], p->d_dd[1], p->d_delays, p->d_csum, p->d_cpad, p->d_lmed};
     for (void *q : dev)
         if (q) (void)hipFree(q);
     for (auto &t : p->ev_pending) {
@@ -872,7 +932,7 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     for (int i = 0; i < 4; ++i)
         if (o.reserved[i]) return FDAS_E_INVAL;
     if (max_series < 1 || max_series > 65535 || !valid_numharm(numharm) || o.K < 1 || o.K > 1024 ||
-        (o.norm != FDAS_NORM_MEDIAN && o.norm != FDAS_NORM_FIXED) ||
+        (o.norm != FDAS_NORM_MEDIAN && o.norm != FDAS_NORM_FIXED && o.norm != FDAS_NORM_LOCAL) ||
         (o.norm == FDAS_NORM_FIXED && !(o.fixed_var > 0)) || o.max_workspace_bytes < 0 ||
         o.max_candidates < 0 || o.harm_order < 0 || o.harm_order > 3 || o.harm_bound < 0 ||
         o.harm_bound > 1 || o.harm_block < 0 || o.harm_block > 64 || o.harm_pair < 0 || o.harm_pair > 1 ||
@@ -1395,6 +1455,8 @@ fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, i
     if (norm_host) {
         if (p->opts.norm == FDAS_NORM_MEDIAN) {
             HIPTRY(p, hipMemcpyAsync(norm_host, p->d_norm, nseries * sizeof(double), hipMemcpyDeviceToHost, st));
+        } else if (p->opts.norm == FDAS_NORM_LOCAL) {
+            for (int b = 0; b < nseries; ++b) norm_host[b] = NAN;
         } else {
             for (int b = 0; b < nseries; ++b) norm_host[b] = (double)nsamp * p->opts.fixed_var;
         }

@@ -62,6 +62,11 @@ hipError_t launch_zero_state(int64_t *state, hipStream_t st);
 size_t median_scratch_bytes(int nseries);
 hipError_t launch_median_scale(const float2 *spec, int64_t spitch, int64_t half, int nseries,
                                float *scale, double *norm, void *scratch, hipStream_t st);
+// Local (red-noise) normalisation in place: bstart[0..nblk] block starts (bstart[0]
+// = 1, bstart[nblk] = half, widths <= 256); med: scratch of nseries * nblk floats;
+// scale[b] is set to 1 (the spectrum itself carries the normalisation).
+hipError_t launch_local_norm(float2 *spec, int64_t spitch, int64_t half, int nseries, const int32_t *bstart,
+                             int nblk, float *med, float *scale, hipStream_t st);
 // scale[0..nseries) = value (the fixed-variance normalisation).
 hipError_t launch_fill_scale(float *scale, int nseries, float value, hipStream_t st);
 

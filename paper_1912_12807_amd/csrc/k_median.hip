@@ -21,9 +21,8 @@ static constexpr int kHistThreads = 256;
 static constexpr int kHistChunk = 8192;     // powers per histogram workgroup
 static constexpr int kBins = 2048;
 
-__device__ __forceinline__ uint32_t power_bits(float2 a) {
-    return __float_as_uint(__fmaf_rn(a.x, a.x, __fmul_rn(a.y, a.y)));
-}
+__device__ __forceinline__ float power_bits_f(float2 a) { return __fmaf_rn(a.x, a.x, __fmul_rn(a.y, a.y)); }
+__device__ __forceinline__ uint32_t power_bits(float2 a) { return __float_as_uint(power_bits_f(a)); }
 
 // state[b] = {prefix, mask, rank, 0}; hist[b][*] = 0.
 __global__ __launch_bounds__(256) void k_med_init(uint32_t *__restrict__ hist, uint4 *__restrict__ state,
@@ -125,6 +124,99 @@ hipError_t launch_median_scale(const float2 *spec, int64_t spitch, int64_t half,
         hipLaunchKernelGGL(k_med_select, dim3(nseries), dim3(64), 0, st, hist, state, shifts[pass], widths[pass],
                            pass == 2 ? 1 : 0, scale, norm);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- local medians
+//
+// Red-noise ("local") normalisation: blocks [b_i, b_{i+1}) of at most 200 bins
+// (host table), m_i = lower median of the block's powers / ln 2 at the block
+// centre c_i = (b_i + b_{i+1} - 1)/2, m(k) linear between neighbouring centres
+// (constant outside), A_k <- A_k / sqrt(m(k)).
+
+// One wave per (block, series): each lane holds up to 4 powers; the median is the
+// element whose count of smaller values is <= rank < count of smaller or equal.
+__global__ __launch_bounds__(64) void k_block_median(const float2 *__restrict__ spec, int64_t spitch,
+                                                     const int32_t *__restrict__ bstart, int nblk,
+                                                     float *__restrict__ med) {
+    __shared__ float s_p[256];
+    const int i = blockIdx.x, b = blockIdx.y, lane = threadIdx.x;
+    const int lo = bstart[i], w = bstart[i + 1] - lo;
+    const float2 *A = spec + (int64_t)b * spitch + lo;
+    float v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = lane + 64 * q;
+        v[q] = k < w ? power_bits_f(A[k]) : __builtin_inff();
+        s_p[k] = v[q];
+    }
+    __syncthreads();
+    const int rank = (w - 1) / 2;
+    float found = -1.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (lane + 64 * q >= w) continue;
+        int less = 0, leq = 0;
+        for (int k = 0; k < w; ++k) {
+            const float u = s_p[k];
+            less += u < v[q];
+            leq += u <= v[q];
+        }
+        if (less <= rank && rank < leq) found = v[q];
+    }
+    // every lane that holds a copy of the median value found the same value
+    const float m = __shfl(found, __ffsll((unsigned long long)__ballot(found >= 0.f)) - 1, 64);
+    if (lane == 0) med[(int64_t)b * nblk + i] = m / 0.69314718055994530942f;
+}
+
+__global__ __launch_bounds__(256) void k_local_apply(float2 *__restrict__ spec, int64_t spitch, int64_t half,
+                                                     const int32_t *__restrict__ bstart, int nblk,
+                                                     const float *__restrict__ med, float *__restrict__ scale) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (k > half) return;
+    float2 *A = spec + (int64_t)b * spitch;
+    if (k == 0 || k == half) {
+        A[k] = make_float2(0.f, 0.f);
+        if (k == 0 && scale) scale[b] = 1.0f;
+        return;
+    }
+    // block j holding k: bstart[j] <= k < bstart[j + 1]
+    int lo = 0, hi = nblk;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bstart[mid] <= k) lo = mid; else hi = mid;
+    }
+    const float *m = med + (int64_t)b * nblk;
+    const float ck = (float)k;
+    const float cj = 0.5f * (float)(bstart[lo] + bstart[lo + 1] - 1);
+    int i0 = ck >= cj ? lo : lo - 1;          // centres c_i0 <= k < c_i0+1
+    float mk;
+    if (i0 < 0) {
+        mk = m[0];
+    } else if (i0 >= nblk - 1) {
+        mk = m[nblk - 1];
+    } else {
+        const float c0 = 0.5f * (float)(bstart[i0] + bstart[i0 + 1] - 1);
+        const float c1 = 0.5f * (float)(bstart[i0 + 1] + bstart[i0 + 2] - 1);
+        mk = m[i0] + (m[i0 + 1] - m[i0]) * ((ck - c0) / (c1 - c0));
+    }
+    const float2 a = A[k];
+    if (mk > 0.f) {
+        const float r = 1.0f / sqrtf(mk);
+        A[k] = make_float2(a.x * r, a.y * r);
+    } else {
+        A[k] = make_float2(0.f, 0.f);
+    }
+}
+
+hipError_t launch_local_norm(float2 *spec, int64_t spitch, int64_t half, int nseries, const int32_t *bstart,
+                             int nblk, float *med, float *scale, hipStream_t st) {
+    if (half < 2 || nseries < 1 || nseries > 65535 || nblk < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_block_median, dim3((unsigned)nblk, (unsigned)nseries), dim3(64), 0, st, spec, spitch,
+                       bstart, nblk, med);
+    hipLaunchKernelGGL(k_local_apply, dim3((unsigned)((half + 1 + 255) / 256), (unsigned)nseries), dim3(256), 0,
+                       st, spec, spitch, half, bstart, nblk, med, scale);
     return hipGetLastError();
 }
 

@@ -247,6 +247,17 @@ def generate_ragged(wl: RaggedWorkload, series_idx=None) -> np.ndarray:
     return out
 
 
+def red_noise_batch(nseries: int, nsamp: int, walk_sd: float, config: int = 88) -> np.ndarray:
+    """float32 [nseries][nsamp]: white N(0,1) noise plus a random walk with steps of
+    sd walk_sd (power falling as 1/f^2: red noise)."""
+    out = np.empty((nseries, nsamp), dtype=np.float32)
+    for b in range(nseries):
+        rng = np.random.Generator(np.random.PCG64(seed_for(config, b)))
+        x = rng.standard_normal(nsamp) + np.cumsum(walk_sd * rng.standard_normal(nsamp))
+        out[b] = x.astype(np.float32)
+    return out
+
+
 def generate(wl: Workload, series_idx=None) -> np.ndarray:
     """float32 [len(series_idx)][nsamp]; default: the whole batch."""
     if series_idx is None:

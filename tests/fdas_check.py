@@ -34,7 +34,11 @@ class OracleSeries:
         self.Z = O.z_index_max(zmax, dz)
         if method is None:
             method = "direct" if self.N <= (1 << 15) else "fft"
-        if plane is None:
+        if plane is None and norm == "local":
+            self.Ah, _ = O.deredden(O.spectrum(x))
+            self.norm = float("nan")
+            self.plane = O.plane(self.Ah, self.rlo, zmax, dz, K, method)
+        elif plane is None:
             self.Ah, self.norm = O.normalise(O.spectrum(x), norm, fixed_var)
             self.plane = O.plane(self.Ah, self.rlo, zmax, dz, K, method)
         else:

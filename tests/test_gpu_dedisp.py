@@ -105,3 +105,28 @@ def test_dedispersed_batch_search_finds_the_pulsars(fast_file):
         near = np.abs(cands["f_hz"] - 1.0 / p.period) <= 2.0 / T
         assert near.any(), p
         assert np.min(np.abs(dm_of[near] - p.dm)) <= 3.0, (p, np.sort(dm_of[near])[:5])
+
+
+def test_sifted_dedispersed_search_keeps_each_pulsar_once(fast_file, fdas_gpu):
+    """Sifting the 979-trial candidate list: every pulsar survives as a strong entry that
+    stands for its detections over many trial DMs around its own DM."""
+    fb, _, plan, buf, series = fast_file
+    offs, ns, ts, dms = [], [], [], []
+    o = 0
+    for (a, s, n, d), sr in zip(fb.plan, series):
+        for i in range(n):
+            offs.append(o + i * sr.shape[1])
+            ns.append(sr.shape[1])
+            ts.append(fb.tsamp * d)
+            dms.append(a + i * s)
+        o += n * sr.shape[1]
+    cands = plan.search_ragged(buf, offs, ns, ts, 0.0, dz=2.0, numharm=8, sigma=7.0, cap=1 << 20)
+    sifted = fdas_gpu.sift(cands)
+    assert 0 < len(sifted) < len(cands) / 5
+    for p in fb.pulsars:
+        f = 1.0 / p.period
+        rows = [r for r in sifted if abs(cands[r["index"]]["f_hz"] - f) <= 2.0 / 52.4288]
+        assert len(rows) == 1, (p, len(rows))
+        r = rows[0]
+        assert r["hits"] >= 5
+        assert dms[r["series_lo"]] <= p.dm + 3.0 and dms[r["series_hi"]] >= p.dm - 3.0
