@@ -187,3 +187,71 @@ def test_pmps_sampled_plane_cells(pmps, fdas_gpu):
     sub = [P[0].cpu().numpy(), P[1].cpu().numpy()]
     del P
     _sampled_plane(sub, lambda b: x[b], wl, [0, 1], n=400)
+
+
+# ----------------------------------------------------------------------------- uneven batch
+
+@pytest.fixture(scope="module")
+def uneven(fdas_gpu):
+    import torch
+    wl = synth.config4()
+    buf = synth.generate_ragged(wl)
+    d = torch.from_numpy(buf).cuda()
+    offs = wl.offsets()
+    plan = fdas_gpu.Plan(max(wl.nsamp), wl.nseries, max(wl.zmax), wl.dz, wl.numharm, autotune=1, graph=1)
+    cands = plan.search_ragged(d, offs, wl.nsamp, wl.tsamp, wl.zmax, sigma=wl.sigma, cap=1 << 21)
+    again = plan.search_ragged(d, offs, wl.nsamp, wl.tsamp, wl.zmax, sigma=wl.sigma, cap=1 << 21)   # replay
+    assert np.array_equal(cands, again)
+    return wl, buf, offs, cands
+
+
+def _series_of(wl, buf, offs, b):
+    return buf[offs[b]:offs[b] + wl.nsamp[b]]
+
+
+def test_uneven_full_candidate_lists_of_two_series(uneven):
+    wl, buf, offs, cands = uneven
+    carriers = {i.series for i in wl.injections}
+    small = [b for b in range(wl.nseries) if wl.nsamp[b] == 1 << 16]
+    picks = [next(b for b in small if b in carriers and wl.zmax[b] >= 100),
+             next(b for b in small if b not in carriers and wl.zmax[b] == 300)]
+    for b in picks:
+        orc = OracleSeries(_series_of(wl, buf, offs, b), wl.tsamp[b], wl.zmax[b], wl.dz, wl.numharm, method="fft")
+        assert_candidates_match(cands[cands["series"] == b], {b: orc}, wl.sigma)
+
+
+def test_uneven_sampled_candidates_verified(uneven):
+    wl, buf, offs, cands = uneven
+    rng = np.random.default_rng(4)
+    series = sorted(set(int(s) for s in cands["series"]))
+    checked = 0
+    for b in sorted(rng.choice(series, min(12, len(series)), replace=False).tolist()):
+        x = _series_of(wl, buf, offs, b)
+        Ah = O.normalise(O.spectrum(x))[0]
+        rlo = O.rlo_bins(wl.nsamp[b], wl.tsamp[b])
+        mine = cands[cands["series"] == b]
+        for H in sorted(set(int(h) for h in mine["harm"])):
+            lst = mine[mine["harm"] == H]
+            if len(lst) > 10:
+                lst = lst[np.sort(rng.choice(len(lst), 10, replace=False))]
+            R = [int(r) for r in lst["r_idx"]]
+            _, M, Zs, S = O.window_maxima(Ah, rlo, wl.zmax[b], wl.dz, H, 0, 0, R_list=R)
+            T = O.threshold(H, wl.sigma)
+            for i, c in enumerate(lst):
+                assert M[i] > T * (1 - REL), (b, H, R[i])
+                assert abs(float(c["power"]) - M[i]) <= REL * max(M[i], 1.0), (b, H, R[i], c["power"], M[i])
+                zg = int(c["z_idx"])
+                if zg != Zs[i]:
+                    assert S[zg + O.z_index_max(wl.zmax[b], wl.dz), i] >= M[i] * (1 - REL)
+                checked += 1
+    assert checked >= 30
+
+
+def test_uneven_injected_pulsars_found(uneven):
+    wl, _, _, cands = uneven
+    found = 0
+    for inj in wl.injections:
+        mine = cands[cands["series"] == inj.series]
+        ok = (np.abs(mine["r_fund"] - inj.r0) <= 1.0) & (np.abs(mine["z_fund"] - inj.z0) <= 2 * wl.dz + 1)
+        found += bool(ok.any())
+    assert found >= len(wl.injections) // 2, (found, len(wl.injections))
