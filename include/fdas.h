@@ -192,8 +192,8 @@ fdas_status fdas_sift(const fdas_cand *cands, int64_t n, double tol_bins, int32_
  * a range with downsampling factor D and trial DM d:
  *   y_c[j] = sum_{s<D} x[j D + s][c],  j < nsamp / D,
  *   delta_c = floor(4.148808e3 d (f_c^-2 - f_hi^-2) / (D tsamp) + 1/2)   (FP64),
- *   out[j] = sum_c y_c[j + delta_c],   y_c read as D m_c past its end,
- *   m_c = floor((sum_t x[t][c] + nsamp/2) / nsamp)  (the channel's rounded mean),
+ *   out[j] = sum_c y_c[j + delta_c],   y_c read as p_c past its end,
+ *   p_c = floor((D sum_t x[t][c] + nsamp/2) / nsamp)  (rounded boxcar mean),
  * with f_c = f0 + c df (MHz) and f_hi the highest channel frequency. All sums
  * are integers below 2^24 (nchan D 255 < 2^24 is required), exact in float32.
  */

@@ -15,9 +15,10 @@ paper does not define the arithmetic; the reading adopted here:
   * the delay in downsampled samples is the nearest integer, computed in FP64 as
         delta_c = floor(KDM * DM * (f_c^-2 - f_hi^-2) / (D * tsamp) + 1/2);
   * the dedispersed series is out[j] = sum_c y_c[j + delta_c], j < nsamp / D,
-    with y_c read past its end as D m_c, m_c = floor((sum_t x_c[t] + nsamp/2) / nsamp)
-    the channel's mean rounded to an integer (so that late samples of high-DM
-    trials keep the series level instead of stepping down).
+    with y_c read past its end as p_c = floor((D sum_t x_c[t] + nsamp/2) / nsamp),
+    the channel's boxcar mean rounded to an integer (so that late samples of
+    high-DM trials keep the series level, to within half a unit per channel,
+    instead of stepping down).
 
 With 8-bit samples every sum is an integer below 2^24, so the result is exact
 in float32 as well as in the int64 used here.
@@ -56,17 +57,18 @@ def downsample(x: np.ndarray, down: int) -> np.ndarray:
     return x.astype(np.int64).reshape(ns // down, down, nc).sum(axis=1).T.copy()
 
 
-def channel_pad(x: np.ndarray) -> np.ndarray:
-    """m_c = floor((sum_t x[t][c] + nsamp // 2) / nsamp): each channel's mean, rounded (int64)."""
+def channel_pad(x: np.ndarray, down: int) -> np.ndarray:
+    """p_c = floor((D sum_t x[t][c] + nsamp // 2) / nsamp): each channel's boxcar mean
+    over D samples, rounded (int64)."""
     ns = x.shape[0]
-    return (x.astype(np.int64).sum(axis=0) + ns // 2) // ns
+    return (int(down) * x.astype(np.int64).sum(axis=0) + ns // 2) // ns
 
 
 def dedisperse(x: np.ndarray, freqs: np.ndarray, tsamp: float, dms: Sequence[float], down: int) -> np.ndarray:
-    """out[i][j] = sum_c y_c[j + delta_c(dms[i])], y_c read as D m_c past its end;
+    """out[i][j] = sum_c y_c[j + delta_c(dms[i])], y_c read as p_c past its end;
     int64 [len(dms)][nsamp/D]."""
     y = downsample(x, down)
-    pad = channel_pad(x) * down
+    pad = channel_pad(x, down)
     nc, n = y.shape
     out = np.zeros((len(dms), n), dtype=np.int64)
     for i, dm in enumerate(dms):

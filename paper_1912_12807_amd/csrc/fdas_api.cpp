@@ -1242,8 +1242,8 @@ fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, 
                                                 ybuf < 0 ? p->d_csum : nullptr, st));
             }
         }
-        if (r == 0) HIPTRY(p, launch_channel_pad(p->d_csum, nsamp, nchan, p->d_cpad, st));
-        HIPTRY(p, launch_dedisperse(p->d_dd[nb], n, n, nchan, p->d_cpad, R.downsamp, p->d_delays + o_del, R.ndm,
+        HIPTRY(p, launch_channel_pad(p->d_csum, nsamp, R.downsamp, nchan, p->d_cpad, st));
+        HIPTRY(p, launch_dedisperse(p->d_dd[nb], n, n, nchan, p->d_cpad, p->d_delays + o_del, R.ndm,
                                     npad[r], group[r], span[r], out_dev + o_out, n, st));
         o_out += (int64_t)R.ndm * n;
         o_del += (int64_t)nchan * npad[r];

@@ -160,20 +160,21 @@ hipError_t launch_argmax(const float *plane, int64_t pitch, int64_t series_strid
 hipError_t launch_fil_downsample(const uint8_t *x, int64_t nsamp, int nchan, int D, float *y, int64_t ypitch,
                                  unsigned long long *sums, hipStream_t st);
 hipError_t launch_zero_sums(unsigned long long *sums, int nchan, hipStream_t st);
-// pad[c] = floor((sums[c] + nsamp/2) / nsamp).
-hipError_t launch_channel_pad(const unsigned long long *sums, int64_t nsamp, int nchan, float *pad, hipStream_t st);
+// pad[c] = floor((D sums[c] + nsamp/2) / nsamp).
+hipError_t launch_channel_pad(const unsigned long long *sums, int64_t nsamp, int D, int nchan, float *pad,
+                              hipStream_t st);
 // out[c][j] = sum_{k<f} in[c][j f + k] for j < n_out, c < nchan.
 hipError_t launch_downsample_rows(const float *in, int64_t ipitch, int64_t n_out, int f, int nchan, float *out,
                                   int64_t opitch, hipStream_t st);
 // LDS row width (floats) that launch_dedisperse stages for a delay spread
 // span_max (0 if the spread is too wide for groups of more than one trial).
 int dedisperse_width(int span_max);
-// out[i][j] = sum_c y[c][j + delays[c][i]] (D pad[c] past n - 1), groups of G trial
+// out[i][j] = sum_c y[c][j + delays[c][i]] (pad[c] past n - 1), groups of G trial
 // DMs per block (G in 1, 2, 4, 8, 16), 16 channels per LDS stage. delays:
 // [nchan][ndm_pad], non-decreasing in i, ndm_pad a multiple of G with entries
 // past ndm repeating the last DM; span_max bounds delays[c][i0 + G - 1] -
 // delays[c][i0] over groups and channels.
-hipError_t launch_dedisperse(const float *y, int64_t ypitch, int64_t n, int nchan, const float *pad, int D,
+hipError_t launch_dedisperse(const float *y, int64_t ypitch, int64_t n, int nchan, const float *pad,
                              const int32_t *delays, int ndm, int ndm_pad, int G, int span_max, float *out,
                              int64_t opitch, hipStream_t st);
 

@@ -3,8 +3,8 @@
 //
 // For one range of trial DMs with downsampling factor D:
 //   y_c[j]   = sum_{d<D} x[j D + d][c]                (boxcar, j < n = nsamp / D)
-//   out_i[j] = sum_c y_c[j + delta_i,c]                (y_c = D m_c past n)
-// with m_c = floor((sum_t x[t][c] + nsamp/2) / nsamp) the channel's rounded mean
+//   out_i[j] = sum_c y_c[j + delta_i,c]                (y_c = p_c past n)
+// with p_c = floor((D sum_t x[t][c] + nsamp/2) / nsamp) the channel's rounded boxcar mean
 // with the integer delays delta_i,c computed on the host. Inputs are 8-bit, so
 // every sum is an integer below 2^24 and float32 holds it exactly: the result
 // does not depend on the summation order.
@@ -65,11 +65,13 @@ __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *__restrict
     if (i < n) v[i] = 0ull;
 }
 
-// m_c = floor((sums[c] + nsamp/2) / nsamp), as float.
+// p_c = floor((D sums[c] + nsamp/2) / nsamp): the channel's boxcar mean, rounded.
 __global__ __launch_bounds__(256) void k_channel_pad(const unsigned long long *__restrict__ sums, int64_t nsamp,
-                                                     int nchan, float *__restrict__ pad) {
+                                                     int D, int nchan, float *__restrict__ pad) {
     const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c < nchan) pad[c] = (float)((sums[c] + (unsigned long long)(nsamp / 2)) / (unsigned long long)nsamp);
+    if (c < nchan)
+        pad[c] = (float)(((unsigned long long)D * sums[c] + (unsigned long long)(nsamp / 2)) /
+                         (unsigned long long)nsamp);
 }
 
 // out[c][j] = sum_{k<f} in[c][j f + k], j < n_out.
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(256) void k_downsample_rows(const float *__restrict
 // counter and stall the reads).
 template <int G, int W>
 __global__ __launch_bounds__(kDdT) void k_dedisperse(const float *__restrict__ y, int64_t ypitch, int64_t n,
-                                                     int nchan, const float *__restrict__ pad, float D,
+                                                     int nchan, const float *__restrict__ pad,
                                                      const int32_t *__restrict__ delays, int ndm, int ndm_pad,
                                                      int chan_split, float *__restrict__ out, int64_t opitch) {
     // fixed-size stage: its LDS address and row stride are compile-time constants,
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(kDdT) void k_dedisperse(const float *__restrict__ y
             const int c = c0 + cc;
             const int64_t base = j0 + delays[(int64_t)c * ndm_pad + dm0];
             const float *row = y + (int64_t)c * ypitch;
-            const float past = D * pad[c];
+            const float past = pad[c];
             for (int k = t; k < W; k += kDdT) {
                 const int64_t idx = base + k;
                 stage[cc][k] = idx < n ? row[idx] : past;
@@ -186,9 +188,10 @@ hipError_t launch_zero_sums(unsigned long long *sums, int nchan, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_channel_pad(const unsigned long long *sums, int64_t nsamp, int nchan, float *pad, hipStream_t st) {
-    if (nsamp < 1 || nchan < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_channel_pad, dim3((nchan + 255) / 256), dim3(256), 0, st, sums, nsamp, nchan, pad);
+hipError_t launch_channel_pad(const unsigned long long *sums, int64_t nsamp, int D, int nchan, float *pad,
+                              hipStream_t st) {
+    if (nsamp < 1 || nchan < 1 || D < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_channel_pad, dim3((nchan + 255) / 256), dim3(256), 0, st, sums, nsamp, D, nchan, pad);
     return hipGetLastError();
 }
 
@@ -206,7 +209,7 @@ int dedisperse_width(int span_max) {
     return 0;
 }
 
-hipError_t launch_dedisperse(const float *y, int64_t ypitch, int64_t n, int nchan, const float *pad, int D,
+hipError_t launch_dedisperse(const float *y, int64_t ypitch, int64_t n, int nchan, const float *pad,
                              const int32_t *delays, int ndm, int ndm_pad, int G, int span_max, float *out,
                              int64_t opitch, hipStream_t st) {
     const int W = dedisperse_width(span_max);
@@ -226,7 +229,7 @@ hipError_t launch_dedisperse(const float *y, int64_t ypitch, int64_t n, int ncha
                            opitch, n);
     }
 #define FDAS_DD(GG, WW)                                                                                        \
-    hipLaunchKernelGGL((k_dedisperse<GG, WW>), grid, dim3(kDdT), 0, st, y, ypitch, n, nchan, pad, (float)D,    \
+    hipLaunchKernelGGL((k_dedisperse<GG, WW>), grid, dim3(kDdT), 0, st, y, ypitch, n, nchan, pad,              \
                        delays, ndm, ndm_pad, chan_split, out, opitch)
 #define FDAS_DDW(GG)                                                                                           \
     switch (W) {                                                                                               \

@@ -38,9 +38,9 @@ def test_brute_force_on_tiny_input():
                 if jj < n:
                     for d in range(D):
                         s += int(x[jj * D + d, c])
-                else:                                   # past the end: D times the rounded mean
+                else:                                   # past the end: the rounded boxcar mean
                     tot = sum(int(v) for v in x[:, c])
-                    s += D * ((2 * tot + nsamp) // (2 * nsamp))
+                    s += (2 * D * tot + nsamp) // (2 * nsamp)
             assert got[i, j] == s, (i, j)
 
 
