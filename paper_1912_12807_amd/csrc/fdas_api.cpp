@@ -497,8 +497,9 @@ fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
     const int64_t sstride = (int64_t)g.NZ * pitch;
     RowBlocks rb;
     TRY(get_rows(p, g.NZ, cg.zgroups, cfg.bz, numharm, cfg.pair != 0, rb));
-    const bool bounded = !p->opts.harm_bound && bounded_lds_bytes(rb.nblk, numharm) <= kBoundLdsMax;
     const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? pitch / 2 : pitch);
+    const bool bounded = !p->opts.harm_bound && bounded_table_bytes(rb.nblk, numharm) <= kBoundTableMax &&
+                         psstride <= kMaxPyrSeriesStride;
     const int NS = nstages_of(numharm);
     const int64_t mpitch = round_up(g.NR, 16);
     int64_t chunk = std::min<int64_t>(p->plane_cap / sstride, p->maxv_cap / (NS * mpitch));
@@ -1388,8 +1389,8 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
                  p->opts.harm_pair == 0, rb));
     const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? g.NR / 2 : g.NR);
     int64_t chunk = std::min<int64_t>(p->max_series, p->maxv_cap / (NS * mpitch));
-    const bool bounded = !p->opts.harm_bound && bounded_lds_bytes(rb.nblk, numharm) <= kBoundLdsMax &&
-                         p->pyr_cap >= psstride;
+    const bool bounded = !p->opts.harm_bound && bounded_table_bytes(rb.nblk, numharm) <= kBoundTableMax &&
+                         psstride <= kMaxPyrSeriesStride && p->pyr_cap >= psstride;
     if (bounded) chunk = std::min<int64_t>(chunk, p->pyr_cap / psstride);
     if (chunk < 1) return p->fail(FDAS_E_INVAL, "one series exceeds the workspace");
     Batch B;

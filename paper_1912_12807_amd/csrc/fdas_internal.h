@@ -99,8 +99,11 @@ void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int
 // Host table of the row blocks each harmonic fraction of each block reads.
 void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
                      const std::vector<int32_t> &of_row, std::vector<int32_t> &frange);
-constexpr size_t kBoundLdsMax = 48 * 1024;
-inline size_t bounded_lds_bytes(int nblk, int numharm) {
+// Limits of the bounded harmonic sums: row-block tables of at most 48 KiB, and
+// block maxima of one series below 4 GiB (32-bit byte offsets in the kernel).
+constexpr size_t kBoundTableMax = 48 * 1024;
+constexpr int64_t kMaxPyrSeriesStride = ((int64_t)1 << 30) - 1;   // floats
+inline size_t bounded_table_bytes(int nblk, int numharm) {
     return (size_t)(nblk + 1 + (size_t)nblk * numharm) * sizeof(int32_t);
 }
 

@@ -151,19 +151,31 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
 
 // Bounded variant: lane = column R, loop over drift blocks. For fraction j the
 // rows a block's sums read, frac_row(zq, j) for zq in the block, lie in row
-// blocks a..e (a host table, staged in LDS; packed as a | (e - a) << 24); the
-// largest block maximum among them (maxima cover both half-bin columns of a
-// bin) bounds every value the fraction contributes. The stage chain of these bounds (same order as the exact
-// chain) bounds every exact stage sum of the block, so a block whose bounds
-// stay at or below all searched stages' thresholds cannot hold a candidate and
-// is skipped. The next block's bounds are loaded while the current one is
-// tested. A block that some lane of the wave cannot rule out is summed exactly
-// by the whole wave.
+// blocks a..e (a host table, packed as a | (e - a) << 24, read through scalar
+// loads since every index is wave-uniform); the largest block maximum among
+// them (maxima cover both half-bin columns of a bin with pairing) bounds every
+// value the fraction contributes. The stage chain of these bounds (same order
+// as the exact chain) bounds every exact stage sum of the block, so a block
+// whose bounds stay at or below all searched stages' thresholds cannot hold a
+// candidate and is skipped. A block that some lane of the wave cannot rule out
+// is summed exactly by the whole wave.
+//
+// A range spans one or two row blocks in all but rare cases: the loads of
+// the first and (under a wave-uniform branch) the second block of every
+// fraction are independent and in flight together, and only longer ranges
+// take a further loop. Block-maxima addresses are a uniform per-series base
+// plus a 32-bit byte offset per lane (one series' maxima stay below 4 GiB).
+// The kernel is bound by the latency of these gathers, so occupancy matters
+// more than sharing the block bookkeeping between many series per lane.
 template <int NH>
 struct BoundCfg {
     // series per lane: the wave-uniform block bookkeeping is shared by SB series
-    static constexpr int SB = NH <= 8 ? 4 : NH == 16 ? 2 : 1;
+    static constexpr int SB = NH <= 16 ? 2 : 1;
 };
+
+__device__ __forceinline__ float load_at(const float *base, uint32_t byte_off) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + byte_off);
+}
 
 template <int NH>
 __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ plane, int64_t pitch,
@@ -177,12 +189,6 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
                                                     int pair, int nseries) {
     constexpr int NS = Stages<NH>::NS;
     constexpr int SB = BoundCfg<NH>::SB;
-    extern __shared__ int32_t sm[];            // blk_lo[nblk + 1], then frange[nblk][NH]
-    for (int i = threadIdx.x; i < nblk + 1; i += 256) sm[i] = blk_lo[i];
-    for (int i = threadIdx.x; i < nblk * NH; i += 256) sm[nblk + 1 + i] = frange[i];
-    __syncthreads();
-    const int32_t *slo = sm;
-    const int32_t *sfr = sm + nblk + 1;
 
     // each XCD (workgroup id mod 8) takes a contiguous run of (series group,
     // column tile) items: neighbouring tiles read overlapping fraction strips
@@ -206,14 +212,18 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         return;
     }
     const int64_t R = c + 2 * rlo;
-    int64_t col[NH];
-    const uint32_t need = column_offsets<NH>(R, rlo, col);
-    // block-maxima column of each fraction (clamped to a valid column when unused)
-    int32_t colp[NH];
+    uint32_t need;
+    // byte offset of each fraction's block-maxima column (clamped to a valid
+    // column when unused)
+    uint32_t cb[NH];
+    {
+        int64_t col[NH];
+        need = column_offsets<NH>(R, rlo, col);
 #pragma unroll
-    for (int j = 0; j < NH; ++j) {
-        const int64_t cc = col[j] < 0 ? 0 : col[j];
-        colp[j] = (int32_t)(pair ? cc >> 1 : cc);
+        for (int j = 0; j < NH; ++j) {
+            const int64_t cc = col[j] < 0 ? 0 : col[j];
+            cb[j] = (uint32_t)(pair ? cc >> 1 : cc) * 4u;
+        }
     }
     const float *yb[SB];
 #pragma unroll
@@ -221,7 +231,7 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         const int bm = b0 + m < nseries ? b0 + m : nseries - 1;   // spare lanes re-read the last series
         yb[m] = pyr + (int64_t)bm * psstride;
     }
-    const int ppitch = (int)(pair ? pitch / 2 : pitch);   // block maxima per bin or per column
+    const uint32_t rowb = (uint32_t)(pair ? pitch / 2 : pitch) * 4u;   // bytes per block-maxima row
     float th[NS];
     bool valid[NS];
 #pragma unroll
@@ -242,29 +252,42 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         for (int m = 0; m < SB; ++m) hotmask[m] = 0;
         const int kend = nblk - k0 < 64 ? nblk - k0 : 64;
         for (int kk = 0; kk < kend; ++kk) {
-            const int32_t *fr = sfr + (k0 + kk) * NH;
-            float B[SB][NH];
-            // first row block of every range: unconditional, independent loads
+            const int32_t *fr = frange + (k0 + kk) * NH;
+            float B[SB][NH], C[SB][NH];
+            int wide = 0;
 #pragma unroll
             for (int j = 0; j < NH; ++j) {
-                const int32_t off = (fr[j] & 0xffffff) * ppitch + colp[j];
+                const int32_t f = fr[j];
+                const int n = f >> 24;
+                wide |= n > 1;
+                const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
 #pragma unroll
-                for (int m = 0; m < SB; ++m) B[m][j] = yb[m][off];
+                for (int m = 0; m < SB; ++m) B[m][j] = load_at(yb[m], o0);
+                if (n > 0) {
+#pragma unroll
+                    for (int m = 0; m < SB; ++m) C[m][j] = load_at(yb[m], o0 + rowb);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < SB; ++m) C[m][j] = 0.0f;
+                }
             }
-            // further row blocks of ranges that span several (wave-uniform branch)
+            if (wide) {
+                // ranges over three or more row blocks (wave-uniform, rare)
 #pragma unroll
-            for (int j = 0; j < NH; ++j) {
-                const int a = fr[j] & 0xffffff, n = fr[j] >> 24;
-                for (int k = 1; k <= n; ++k) {
-                    const int32_t off = (a + k) * ppitch + colp[j];
+                for (int j = 0; j < NH; ++j) {
+                    const int32_t f = fr[j];
+                    const int n = f >> 24;
+                    for (int k = 2; k <= n; ++k) {
+                        const uint32_t o = (uint32_t)((f & 0xffffff) + k) * rowb + cb[j];
 #pragma unroll
-                    for (int m = 0; m < SB; ++m) B[m][j] = fmaxf(B[m][j], yb[m][off]);
+                        for (int m = 0; m < SB; ++m) B[m][j] = fmaxf(B[m][j], load_at(yb[m], o));
+                    }
                 }
             }
 #pragma unroll
             for (int m = 0; m < SB; ++m) {
 #pragma unroll
-                for (int j = 0; j < NH; ++j) B[m][j] = ((need >> j) & 1u) ? B[m][j] : 0.0f;
+                for (int j = 0; j < NH; ++j) B[m][j] = ((need >> j) & 1u) ? fmaxf(B[m][j], C[m][j]) : 0.0f;
                 float U[NS];
                 stage_chain<NH>(B[m], U);
                 bool hot = false;
@@ -274,6 +297,12 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
             }
         }
         // pass 2: exact sums of the hot blocks
+        uint64_t any_hot = 0;
+#pragma unroll
+        for (int m = 0; m < SB; ++m) any_hot |= hotmask[m];
+        if (!any_hot) continue;
+        int64_t col[NH];
+        (void)column_offsets<NH>(R, rlo, col);
 #pragma unroll
         for (int m = 0; m < SB; ++m) {
             if (b0 + m >= nseries) break;
@@ -282,7 +311,7 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
             while (hm) {
                 const int kb = k0 + __builtin_ctzll(hm);
                 hm &= hm - 1;
-                const int zqa = slo[kb] - Z, zqb = slo[kb + 1] - 1 - Z;
+                const int zqa = blk_lo[kb] - Z, zqb = blk_lo[kb + 1] - 1 - Z;
                 for (int zq = zqa; zq <= zqb; ++zq) {
                     float P[NH], Ss[NS];
                     gather<NH>(pb, pitch, Z, zq, col, need, P);
@@ -535,8 +564,7 @@ static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, 
     const int64_t groups = (nseries + BoundCfg<NH>::SB - 1) / BoundCfg<NH>::SB;
     const int64_t total = tps * groups;
     const int64_t nwg = 8 * ((total + 7) / 8);
-    const size_t lds = (size_t)(rb.nblk + 1 + rb.nblk * NH) * sizeof(int32_t);
-    hipLaunchKernelGGL(k_harm_bound<NH>, dim3((unsigned)nwg), dim3(256), lds, st, plane, pitch, sstride,
+    hipLaunchKernelGGL(k_harm_bound<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
                        pyr, psstride, rb.lo, rb.frange, rb.nblk, NR, rlo, Z, thr, maxv, mpitch, tps, total,
                        rb.pair ? 1 : 0, nseries);
 }
@@ -548,7 +576,7 @@ hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t ser
     // block-maxima offsets within one series are 32-bit in the kernel
     if (nseries < 1 || mpitch < NR || (mpitch & 15) || (mpitch + 255) / 256 * nseries > 0x7ffffff0LL ||
         !pyr || !rb.lo || !rb.frange || rb.nblk < 1 || rb.frange_nh != numharm ||
-        bounded_lds_bytes(rb.nblk, numharm) > kBoundLdsMax || pyr_series_stride > 0x7fffffffLL)
+        bounded_table_bytes(rb.nblk, numharm) > kBoundTableMax || pyr_series_stride > kMaxPyrSeriesStride)
         return hipErrorInvalidValue;
 #define FDAS_BOUND(NHV) launch_bound_nh<NHV>(plane, pitch, series_stride, pyr, pyr_series_stride, rb, NR, rlo, Z, nseries, thr_dev, maxv, mpitch, st)
     switch (numharm) {
