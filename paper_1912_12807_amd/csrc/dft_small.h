@@ -7,6 +7,22 @@
 
 namespace fdas {
 
+// IEEE half bits of a half >= x for x >= 0: the nearest half, stepped up once
+// when it lies below x (+inf above the largest finite half; NaN stays NaN), and
+// never a subnormal (positive x below the smallest normal half gives that
+// half), so the bound holds whether or not subnormals are flushed. Block
+// maxima stored this way still bound every power of their block.
+__device__ __forceinline__ uint16_t bound_half(float x) {
+    const _Float16 h = (_Float16)x;                 // round to nearest even
+    uint16_t u = __builtin_bit_cast(uint16_t, h);
+    if ((float)h < x) ++u;                          // next half up (finite, non-negative)
+    if (u < 0x0400u && x > 0.0f) u = 0x0400u;       // smallest normal half, 2^-14
+    return u;
+}
+__device__ __forceinline__ float half_bits_to_float(uint16_t u) {
+    return (float)__builtin_bit_cast(_Float16, u);
+}
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {

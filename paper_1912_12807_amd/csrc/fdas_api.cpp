@@ -152,8 +152,8 @@ struct fdas_plan_s {
     int64_t nblk_cap = 0;
     DevCand *d_rec = nullptr;
     int64_t rec_cap = 0;
-    float *d_pyr = nullptr;
-    int64_t pyr_cap = 0;        // floats
+    bmax_t *d_pyr = nullptr;    // block maxima (half bits, rounded up)
+    int64_t pyr_cap = 0;        // halves
     int last_harm_blocks = 0, last_harm_pair = 0;
     int last_L = 0, last_mseg = 0, last_NZ = 0;
     // pinned host staging

@@ -99,20 +99,24 @@ void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int
 // Host table of the row blocks each harmonic fraction of each block reads.
 void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
                      const std::vector<int32_t> &of_row, std::vector<int32_t> &frange);
+// Block maxima are stored as IEEE half bits rounded upward (+inf above the
+// largest half), so every stored value still bounds the powers of its block.
+using bmax_t = uint16_t;
 // Limits of the bounded harmonic sums: row-block tables of at most 48 KiB, and
 // block maxima of one series below 4 GiB (32-bit byte offsets in the kernel).
 constexpr size_t kBoundTableMax = 48 * 1024;
-constexpr int64_t kMaxPyrSeriesStride = ((int64_t)1 << 30) - 1;   // floats
+constexpr int64_t kMaxPyrSeriesStride = ((int64_t)1 << 31) - 1;   // halves
 inline size_t bounded_table_bytes(int nblk, int numharm) {
     return (size_t)(nblk + 1 + (size_t)nblk * numharm) * sizeof(int32_t);
 }
 
 // K4. If pyr is not null, K4 also writes the block maxima: pyr[b][k][c] = max
 // over the rows of block k of plane[b][row][c] (pitch = plane pitch), or with
-// rb.pair the maximum over columns 2i and 2i+1 at pyr[b][k][i] (pitch / 2).
+// rb.pair the maximum over columns 2i and 2i+1 at pyr[b][k][i] (pitch / 2),
+// rounded up to half precision.
 hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *scale,
                              const float2 *bank, const CorrGeom &g, int nseries, float *plane,
-                             int64_t pitch, int64_t series_stride, float *pyr,
+                             int64_t pitch, int64_t series_stride, bmax_t *pyr,
                              int64_t pyr_series_stride, const RowBlocks &rb, hipStream_t st);
 
 // K5: harmonic sums and maxima over z for every column and stage.
@@ -126,7 +130,7 @@ hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stri
 
 // Block maxima of a caller-supplied plane (what K4 writes alongside its plane).
 hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
-                            const RowBlocks &rb, int nseries, float *pyr, int64_t pyr_series_stride,
+                            const RowBlocks &rb, int nseries, bmax_t *pyr, int64_t pyr_series_stride,
                             hipStream_t st);
 
 // K5 with block bounds: per column and drift block, the stage chain over the
@@ -136,7 +140,7 @@ hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_st
 // the threshold (elsewhere it only stays at or below it), so the candidates
 // equal those of launch_harmsum bit for bit.
 hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
-                                  const float *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
+                                  const bmax_t *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
                                   int64_t NR, int64_t rlo, int Z, int numharm, int nseries,
                                   const float *thr_dev, float *maxv, int64_t mpitch, hipStream_t st);
 

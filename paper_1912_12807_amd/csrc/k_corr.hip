@@ -171,7 +171,7 @@ __global__ __launch_bounds__(L / 8, FDAS_K4_MIN_WAVES) void k_corr_power(const f
                                                       const float2 *__restrict__ bank, CorrGeom g,
                                                       int nseries, float *__restrict__ plane,
                                                       int64_t pitch, int64_t sstride,
-                                                      float *__restrict__ pyr, int64_t psstride,
+                                                      bmax_t *__restrict__ pyr, int64_t psstride,
                                                       const int32_t *__restrict__ blk_lo,
                                                       const int32_t *__restrict__ blk_of_row) {
     constexpr int T = Corr<L>::T;
@@ -216,9 +216,9 @@ __global__ __launch_bounds__(L / 8, FDAS_K4_MIN_WAVES) void k_corr_power(const f
     for (int q = 0; q < 8; ++q) S[q] = make_float2(S[q].x * sc, S[q].y * sc);
 
     float *out = plane + (int64_t)b * sstride + 2 * (ks - g.rlo);
-    // block-maxima row: pitch floats per block (PYR 1), pitch/2 (PYR 2)
+    // block-maxima row: pitch halves per block (PYR 1), pitch/2 (PYR 2)
     const int64_t ppitch = PYR == 2 ? pitch / 2 : pitch;
-    float *pout = PYR ? pyr + (int64_t)b * psstride + (PYR == 2 ? 1 : 2) * (ks - g.rlo) : nullptr;
+    bmax_t *pout = PYR ? pyr + (int64_t)b * psstride + (PYR == 2 ? 1 : 2) * (ks - g.rlo) : nullptr;
     int blk = 0, blk_end = 0;
     float m0[8], m1[8];
     if constexpr (PYR != 0) {
@@ -249,13 +249,17 @@ __global__ __launch_bounds__(L / 8, FDAS_K4_MIN_WAVES) void k_corr_power(const f
         }
         if constexpr (PYR != 0) {
             if (zi + 1 == blk_end) {
-                float *prow = pout + (int64_t)blk * ppitch;
+                bmax_t *prow = pout + (int64_t)blk * ppitch;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int i = t + q * T;
                     if (i < g.Lv && ks + i < g.half) {
-                        if constexpr (PYR == 2) prow[i] = m0[q];
-                        else *reinterpret_cast<float2 *>(prow + 2 * i) = make_float2(m0[q], m1[q]);
+                        if constexpr (PYR == 2) {
+                            prow[i] = bound_half(m0[q]);
+                        } else {
+                            const uint32_t two = (uint32_t)bound_half(m0[q]) | ((uint32_t)bound_half(m1[q]) << 16);
+                            *reinterpret_cast<uint32_t *>(prow + 2 * i) = two;
+                        }
                     }
                     m0[q] = m1[q] = 0.0f;
                 }
@@ -305,7 +309,7 @@ void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
 template <int L>
 static void launch_l(const float2 *spec, int64_t spitch, const float *scale, const float2 *bank,
                      const CorrGeom &g, int nseries, float *plane, int64_t pitch, int64_t sstride,
-                     float *pyr, int64_t psstride, const RowBlocks &rb, int64_t nwg, hipStream_t st) {
+                     bmax_t *pyr, int64_t psstride, const RowBlocks &rb, int64_t nwg, hipStream_t st) {
     const int mode = pyr ? (rb.pair ? 2 : 1) : 0;
 #define FDAS_K4(M)                                                                                  \
     hipLaunchKernelGGL((k_corr_power<L, M>), dim3((unsigned)nwg), dim3(L / 8), 0, st, spec, spitch, \
@@ -318,7 +322,7 @@ static void launch_l(const float2 *spec, int64_t spitch, const float *scale, con
 
 hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *scale,
                              const float2 *bank, const CorrGeom &g, int nseries, float *plane,
-                             int64_t pitch, int64_t series_stride, float *pyr,
+                             int64_t pitch, int64_t series_stride, bmax_t *pyr,
                              int64_t pyr_series_stride, const RowBlocks &rb, hipStream_t st) {
     if (nseries < 1 || g.nseg < 1 || g.Lv < 1 || (g.zgroups & (g.zgroups - 1)) || g.zgroups > 8 ||
         g.zgroups < 1 || (pitch & 1) || (pyr && (!rb.lo || !rb.of_row || rb.nblk < 1)))

@@ -153,33 +153,33 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
 // rows a block's sums read, frac_row(zq, j) for zq in the block, lie in row
 // blocks a..e (a host table, packed as a | (e - a) << 24, read through scalar
 // loads since every index is wave-uniform); the largest block maximum among
-// them (maxima cover both half-bin columns of a bin with pairing) bounds every
-// value the fraction contributes. The stage chain of these bounds (same order
+// them (maxima cover both half-bin columns of a bin with pairing; stored as
+// halves rounded up) bounds every value the fraction contributes. The stage chain of these bounds (same order
 // as the exact chain) bounds every exact stage sum of the block, so a block
 // whose bounds stay at or below all searched stages' thresholds cannot hold a
 // candidate and is skipped. A block that some lane of the wave cannot rule out
 // is summed exactly by the whole wave.
 //
 // A range spans one or two row blocks in all but rare cases: the loads of
-// the first and (under a wave-uniform branch) the second block of every
-// fraction are independent and in flight together, and only longer ranges
-// take a further loop. Block-maxima addresses are a uniform per-series base
+// the first and second block of every fraction are independent and in flight
+// together, and only longer ranges take a further loop. Block-maxima addresses are a uniform per-series base
 // plus a 32-bit byte offset per lane (one series' maxima stay below 4 GiB).
+// Maxima are gathered as halves (half the bytes and cache lines).
 // The kernel is bound by the latency of these gathers, so occupancy matters
 // more than sharing the block bookkeeping between many series per lane.
 template <int NH>
 struct BoundCfg {
     // series per lane: the wave-uniform block bookkeeping is shared by SB series
-    static constexpr int SB = NH <= 16 ? 2 : 1;
+    static constexpr int SB = NH <= 8 ? 2 : 1;
 };
 
-__device__ __forceinline__ float load_at(const float *base, uint32_t byte_off) {
-    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + byte_off);
+__device__ __forceinline__ float load_at(const bmax_t *base, uint32_t byte_off) {
+    return half_bits_to_float(*reinterpret_cast<const bmax_t *>(reinterpret_cast<const char *>(base) + byte_off));
 }
 
 template <int NH>
 __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ plane, int64_t pitch,
-                                                    int64_t sstride, const float *__restrict__ pyr,
+                                                    int64_t sstride, const bmax_t *__restrict__ pyr,
                                                     int64_t psstride, const int32_t *__restrict__ blk_lo,
                                                     const int32_t *__restrict__ frange, int nblk,
                                                     int64_t NR, int64_t rlo, int Z,
@@ -222,16 +222,16 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
 #pragma unroll
         for (int j = 0; j < NH; ++j) {
             const int64_t cc = col[j] < 0 ? 0 : col[j];
-            cb[j] = (uint32_t)(pair ? cc >> 1 : cc) * 4u;
+            cb[j] = (uint32_t)(pair ? cc >> 1 : cc) * (uint32_t)sizeof(bmax_t);
         }
     }
-    const float *yb[SB];
+    const bmax_t *yb[SB];
 #pragma unroll
     for (int m = 0; m < SB; ++m) {
         const int bm = b0 + m < nseries ? b0 + m : nseries - 1;   // spare lanes re-read the last series
         yb[m] = pyr + (int64_t)bm * psstride;
     }
-    const uint32_t rowb = (uint32_t)(pair ? pitch / 2 : pitch) * 4u;   // bytes per block-maxima row
+    const uint32_t rowb = (uint32_t)(pair ? pitch / 2 : pitch) * (uint32_t)sizeof(bmax_t);   // bytes per row
     float th[NS];
     bool valid[NS];
 #pragma unroll
@@ -253,6 +253,9 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         const int kend = nblk - k0 < 64 ? nblk - k0 : 64;
         for (int kk = 0; kk < kend; ++kk) {
             const int32_t *fr = frange + (k0 + kk) * NH;
+            // both row blocks of every range (the same one twice when e = a):
+            // no branch, so no conversion can be placed where it would wait
+            // for all earlier loads
             float B[SB][NH], C[SB][NH];
             int wide = 0;
 #pragma unroll
@@ -261,14 +264,11 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
                 const int n = f >> 24;
                 wide |= n > 1;
                 const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
+                const uint32_t o1 = n > 0 ? o0 + rowb : o0;
 #pragma unroll
-                for (int m = 0; m < SB; ++m) B[m][j] = load_at(yb[m], o0);
-                if (n > 0) {
-#pragma unroll
-                    for (int m = 0; m < SB; ++m) C[m][j] = load_at(yb[m], o0 + rowb);
-                } else {
-#pragma unroll
-                    for (int m = 0; m < SB; ++m) C[m][j] = 0.0f;
+                for (int m = 0; m < SB; ++m) {
+                    B[m][j] = load_at(yb[m], o0);
+                    C[m][j] = load_at(yb[m], o1);
                 }
             }
             if (wide) {
@@ -371,10 +371,11 @@ __global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ plane,
 // Block maxima of a caller-supplied plane (what K4 writes while it builds the
 // plane): per column, pyr[b][k][c] = max over the rows of block k of
 // plane[b][row][c]; with pair, pyr[b][k][i] covers columns 2i and 2i+1.
+// Stored rounded up to half precision, like K4's.
 __global__ __launch_bounds__(256) void k_block_max(const float *__restrict__ plane, int64_t pitch,
                                                    int64_t sstride, int64_t NR,
                                                    const int32_t *__restrict__ blk_lo, int nblk,
-                                                   float *__restrict__ pyr, int64_t psstride, int pair) {
+                                                   bmax_t *__restrict__ pyr, int64_t psstride, int pair) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int k = blockIdx.y, b = blockIdx.z;
     const int64_t ncol = pair ? NR / 2 : NR;
@@ -385,11 +386,11 @@ __global__ __launch_bounds__(256) void k_block_max(const float *__restrict__ pla
         const float *q = src + (int64_t)r * pitch;
         mx = fmaxf(mx, pair ? fmaxf(q[0], q[1]) : q[0]);
     }
-    pyr[(int64_t)b * psstride + (int64_t)k * (pair ? pitch / 2 : pitch) + i] = mx;
+    pyr[(int64_t)b * psstride + (int64_t)k * (pair ? pitch / 2 : pitch) + i] = bound_half(mx);
 }
 
 hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
-                            const RowBlocks &rb, int nseries, float *pyr, int64_t pyr_series_stride,
+                            const RowBlocks &rb, int nseries, bmax_t *pyr, int64_t pyr_series_stride,
                             hipStream_t st) {
     if (nseries < 1 || nseries > 65535 || rb.nblk < 1 || rb.nblk > 65535 || !rb.lo || (pitch & 1) ||
         (NR & 1))
@@ -557,7 +558,7 @@ hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stri
 }
 
 template <int NH>
-static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, const float *pyr,
+static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, const bmax_t *pyr,
                             int64_t psstride, const RowBlocks &rb, int64_t NR, int64_t rlo, int Z,
                             int nseries, const float *thr, float *maxv, int64_t mpitch, hipStream_t st) {
     const int64_t tps = (mpitch + 255) / 256;
@@ -570,7 +571,7 @@ static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, 
 }
 
 hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
-                                  const float *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
+                                  const bmax_t *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
                                   int64_t NR, int64_t rlo, int Z, int numharm, int nseries,
                                   const float *thr_dev, float *maxv, int64_t mpitch, hipStream_t st) {
     // block-maxima offsets within one series are 32-bit in the kernel

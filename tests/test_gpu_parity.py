@@ -254,6 +254,7 @@ BOUND_CASES = [
     (2, 1 << 13, 1e-3, 0.0, 2.0, 4, 4.0, 0),      # one drift row
     (2, 1 << 14, 1e-3, 60.0, 2.0, 8, 5.0, 1),     # one row per block
     (2, 1 << 14, 1e-3, 60.0, 2.0, 8, 5.0, 61),    # one block per z group
+    (2, 1 << 14, 1e-3, 100.0, 2.0, 8, 4.0, 6),    # a fraction range over three row blocks
 ]
 
 
@@ -287,4 +288,58 @@ def test_bounded_harmsum_bit_exact_on_the_same_float_plane(fdas_gpu, numharm, bz
     ref = fdas_gpu.Plan(N, B, zmax, dz, numharm, harm_bound=1).harmsum(P, N, ts, sigma=sig, cap=1 << 18)
     got = fdas_gpu.Plan(N, B, zmax, dz, numharm, harm_block=bz).harmsum(P, N, ts, sigma=sig, cap=1 << 18)
     assert len(ref) > 20
+    assert np.array_equal(ref, got)
+
+
+@pytest.mark.parametrize("harm_pair", [0, 1], ids=["maxima-per-bin", "maxima-per-column"])
+def test_bounded_harmsum_exact_near_thresholds_and_at_half_precision_extremes(fdas_gpu, harm_pair):
+    """Block maxima are stored as halves rounded up: cells a fraction of a half ulp
+    above (or around) a stage threshold, powers beyond the largest half and
+    powers below the smallest normal half must not change any candidate."""
+    import torch
+    B, N, ts, zmax, dz, nh, sigma = 2, 1 << 14, 1e-3, 30.0, 2.0, 8, 6.0
+    rlo = O.rlo_bins(N, ts)
+    Z = O.z_index_max(zmax, dz)
+    NZ, NR = 2 * Z + 1, N - 2 * rlo
+    rng = np.random.default_rng(4242)
+    P = (rng.exponential(1.0, (B, NZ, NR)) * 10.0 ** rng.uniform(-9.0, 0.0, (B, NZ, NR))).astype(np.float32)
+    T = {H: np.float32(O.threshold(H, sigma)) for H in (1, 2, 4, 8)}
+    for b in range(B):
+        # stage 1: single cells at the next float above T_1, or within 2^-10 of it
+        rows = rng.integers(0, NZ, 400)
+        cols = rng.integers(0, NR, 400)
+        vals = (T[1] * (1.0 + rng.uniform(-2.0 ** -10, 2.0 ** -10, 400))).astype(np.float32)
+        vals[:100] = np.nextafter(T[1], np.float32(np.inf))
+        P[b, rows, cols] = vals
+        # stage 8 on the zero-drift row: all eight harmonics near T_8 / 8
+        for R in rng.integers(2 * rlo * 8, N, 150):
+            u = np.float32(T[8] / 8.0 * (1.0 + rng.uniform(-2.0 ** -10, 2.0 ** -10)))
+            for k in range(1, 9):
+                P[b, Z, (2 * int(R) * k + 8) // 16 - 2 * rlo] = u
+        # beyond the largest finite half
+        P[b, rng.integers(0, NZ, 5), rng.integers(0, NR, 5)] = np.float32([7e4, 1e6, 1e9, 1e20, 1e30])
+    Pt = torch.from_numpy(P).cuda()
+    ref = fdas_gpu.Plan(N, B, zmax, dz, nh, harm_bound=1).harmsum(Pt, N, ts, sigma=sigma, cap=1 << 18)
+    got = fdas_gpu.Plan(N, B, zmax, dz, nh, harm_pair=harm_pair).harmsum(Pt, N, ts, sigma=sigma, cap=1 << 18)
+    assert len(ref) > 400
+    assert np.array_equal(ref, got)
+
+
+def test_bounded_search_exact_with_powers_beyond_the_largest_half(fdas_gpu):
+    """Strong signals make plane powers far above 65504 (maxima stored as +inf)."""
+    B, N, ts, zmax, dz, nh = 2, 1 << 14, 1e-3, 40.0, 2.0, 8
+    rng = np.random.default_rng(98)
+    t = np.arange(N) * ts
+    T = N * ts
+    x = rng.standard_normal((B, N))
+    for b, (f, z, amp) in enumerate([(101.3, 12.0, 40.0), (37.77, -30.0, 25.0)]):
+        # drifting sinusoid: z bins of frequency drift over the observation
+        x[b] += amp * np.cos(2 * np.pi * (f * t + 0.5 * z / T ** 2 * t ** 2))
+    x = _cuda(x.astype(np.float32))
+    plan = fdas_gpu.Plan(N, B, zmax, dz, nh)
+    P = plan.plane(x, ts)
+    assert float(P.max()) > 1e5
+    ref = fdas_gpu.Plan(N, B, zmax, dz, nh, harm_bound=1).search(x, ts, sigma=6.0, cap=1 << 18)
+    got = plan.search(x, ts, sigma=6.0, cap=1 << 18)
+    assert len(ref) > 5
     assert np.array_equal(ref, got)
