@@ -535,6 +535,7 @@ fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
         e = p->begin(st);
         HIPTRY(p, launch_argmax(p->d_plane, pitch, sstride, g.rlo, g.Z, numharm, vbase + b0, p->d_rec,
                                 p->d_state, p->rec_cap, st));
+        HIPTRY(p, launch_cand_sigma(p->d_rec, p->d_state, p->rec_cap, st));
         p->end(5, e, st);
     }
     return FDAS_OK;
@@ -671,12 +672,6 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
         HIPTRY(p, hipStreamSynchronize(st));
     }
     p->collect();
-    std::vector<fdas_cand> all;
-    fdas_cand *dst = out;
-    if (!sorted_on_device) {
-        all.resize((size_t)n);
-        dst = all.data();
-    }
     for (int64_t i = 0; i < n; ++i) {
         const DevCand &d = p->h_rec[i];
         if (d.b < 0 || d.b >= (int)B.vmap.size() || d.s < 0 || d.s > 5)
@@ -685,20 +680,37 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
         if (d.zq < -g.Z || d.zq > g.Z)
             return p->fail(FDAS_E_DEVICE, "internal error: candidate without a maximising drift");
     }
-    // units and FP64 significance, over host threads for long lists
+    // Device records are in (batch slot, stage, column) order, and each slot
+    // holds one caller series: a stable counting sort by caller series gives
+    // the (series, harm, r_idx) order. Only the first cap ranks are written.
+    std::vector<int64_t> rank;
+    if (!sorted_on_device) {
+        int ns = 0;
+        for (int v : B.vmap) ns = std::max(ns, v + 1);
+        std::vector<int64_t> next((size_t)ns + 1, 0);
+        for (int64_t i = 0; i < n; ++i) ++next[(size_t)B.vmap[p->h_rec[i].b] + 1];
+        for (int k = 0; k < ns; ++k) next[k + 1] += next[k];
+        rank.resize((size_t)n);
+        for (int64_t i = 0; i < n; ++i) rank[i] = next[B.vmap[p->h_rec[i].b]]++;
+    }
+    const int64_t lim = std::min(n, cap);
+    // units (the FP64 significance comes from the device), over host threads
+    // for long lists
     auto convert = [&](int64_t i0, int64_t i1) {
         for (int64_t i = i0; i < i1; ++i) {
+            const int64_t k = rank.empty() ? i : rank[i];
+            if (k >= lim) continue;
             const DevCand &d = p->h_rec[i];
             const Geometry &g = B.groups[B.vgroup[d.b]].g;
             const int H = 1 << d.s;
             const double T = B.vT[d.b];
-            fdas_cand &c = dst[i];
+            fdas_cand &c = out[k];
             c.series = B.vmap[d.b];
             c.harm = H;
             c.r_idx = (int64_t)d.c + 2 * g.rlo;
             c.z_idx = d.zq;
             c.power = d.power;
-            c.sigma = sigma_of(H, (double)d.power);
+            c.sigma = d.sigma;
             c.r_fund = (double)c.r_idx / (2.0 * H);
             c.z_fund = (double)d.zq * dz / H;
             c.f_hz = c.r_fund / T;
@@ -714,15 +726,6 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
         std::vector<std::thread> pool;
         for (int w = 0; w < nth; ++w) pool.emplace_back(convert, n * w / nth, n * (w + 1) / nth);
         for (auto &t : pool) t.join();
-    }
-    if (!sorted_on_device) {
-        std::stable_sort(all.begin(), all.end(), [](const fdas_cand &a, const fdas_cand &b) {
-            if (a.series != b.series) return a.series < b.series;
-            if (a.harm != b.harm) return a.harm < b.harm;
-            return a.r_idx < b.r_idx;
-        });
-        const int64_t m = std::min<int64_t>(cap, n);
-        if (m > 0) std::memcpy(out, all.data(), (size_t)m * sizeof(fdas_cand));
     }
     *n_total = total;
     return total > cap ? FDAS_E_TRUNC : FDAS_OK;
@@ -1424,6 +1427,7 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
             e = p->begin(st);
             HIPTRY(p, launch_argmax(pl, g.NR, sstride, g.rlo, g.Z, numharm, b0, p->d_rec, p->d_state, p->rec_cap,
                                     st));
+            HIPTRY(p, launch_cand_sigma(p->d_rec, p->d_state, p->rec_cap, st));
             p->end(5, e, st);
         }
         bool regrow = false;

@@ -41,7 +41,8 @@ struct DevCand {
     int32_t c;       // column: R = c + 2 rlo
     int32_t zq;      // smallest maximising z index (filled by the argmax kernel)
     float power;     // M_H(R)
-    int32_t pad[3];
+    int32_t pad;
+    double sigma;    // significance of power at stage H (filled by launch_cand_sigma)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -159,6 +160,8 @@ hipError_t launch_compact(const float *maxv, int64_t nelem, int64_t mpitch, int 
 hipError_t launch_argmax(const float *plane, int64_t pitch, int64_t series_stride, int64_t rlo,
                          int Z, int numharm, int b0, DevCand *rec, const int64_t *state,
                          int64_t cap, hipStream_t st);
+// FP64 significance of the same records (the host statistics' arithmetic).
+hipError_t launch_cand_sigma(DevCand *rec, const int64_t *state, int64_t cap, hipStream_t st);
 
 // K0: dedispersion. x: time-major uint8 [nsamp][nchan]; y: channel-major float
 // rows [nchan][ypitch] of boxcar sums over D samples (n = nsamp / D outputs).

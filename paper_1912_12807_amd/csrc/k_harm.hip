@@ -479,7 +479,8 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ maxv,
                 d.c = (int32_t)(c0 + i);
                 d.zq = INT_MAX;
                 d.power = v[i];
-                d.pad[0] = d.pad[1] = d.pad[2] = 0;
+                d.pad = 0;
+                d.sigma = 0.0;
                 out[o] = d;
             }
             ++o;

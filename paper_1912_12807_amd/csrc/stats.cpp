@@ -28,15 +28,29 @@ static double log_factorial(int j) {
     return j < 65 ? t.v[j] : std::lgamma(j + 1.0);
 }
 
-// log Q(H, S) by a log-sum-exp over the H terms of the finite series.
+// log Q(H, S). At or above the mean (S >= H) from the H terms S^j / j! of the
+// finite series scaled by the largest, j = H - 1: each term is the next one
+// times j / S, so only two logarithms are needed.
 double log_gamma_sf(int H, double S) {
     if (S <= 0.0) return 0.0;
-    double ls = std::log(S);
-    double mx = -INFINITY;
-    for (int j = 0; j < H; ++j) mx = std::fmax(mx, j * ls - log_factorial(j));
-    double acc = 0.0;
-    for (int j = 0; j < H; ++j) acc += std::exp(j * ls - log_factorial(j) - mx);
-    return -S + mx + std::log(acc);
+    const double ls = std::log(S);
+    if (S < H) {
+        // below the mean Q is close to 1: log1p of minus the lower tail
+        // P(H, S) = exp(-S) sum_{j >= H} S^j / j!, whose terms shrink by S / j
+        double term = 1.0, acc = 1.0;   // scaled by S^H / H!
+        for (int j = H + 1; j < H + 400; ++j) {
+            term *= S / j;
+            acc += term;
+            if (term < 1e-17 * acc) break;
+        }
+        return std::log1p(-std::exp(-S + H * ls - log_factorial(H) + std::log(acc)));
+    }
+    double acc = 1.0, r = 1.0;
+    for (int j = H - 1; j > 0; --j) {   // terms j - 1 down to 0
+        r *= j / S;
+        acc += r;
+    }
+    return -S + ((H - 1) * ls - log_factorial(H - 1)) + std::log(acc);
 }
 
 // d/dS log Q(H, S) = -(S^(H-1)/(H-1)!) exp(-S) / Q(H, S).
@@ -46,6 +60,7 @@ static double dlog_gamma_sf(int H, double S, double logq) {
 
 // log of the Gaussian upper tail, log(erfc(s / sqrt 2) / 2), for any s.
 double log_gauss_tail(double s) {
+    if (s < 0.0) return std::log1p(-0.5 * std::erfc(-s / std::sqrt(2.0)));   // tail near 1
     if (s < 25.0) return std::log(0.5 * std::erfc(s / std::sqrt(2.0)));
     // asymptotic series of the Mills ratio: tail = phi(s)/s * sum (-1)^n (2n-1)!! / s^(2n)
     double inv2 = 1.0 / (s * s);
@@ -86,18 +101,30 @@ double threshold(int H, double sigma) {
 
 double sigma_of(int H, double power) {
     const double lq = log_gamma_sf(H, power);
-    // solve log_gauss_tail(s) = lq; start from the leading-order inversion
+    // solve log_gauss_tail(s) = lq; start from the leading-order inversion.
+    // Safeguarded Newton (bisection when a step leaves the bracket); once a
+    // Newton step is below 1e-7 one more step reaches the rounding level of
+    // the tail evaluation (waiting for steps below 1e-14 instead left it
+    // hovering there between the brackets for dozens of iterations)
     double s = (lq < -1.0) ? std::sqrt(std::fmax(0.0, -2.0 * lq - std::log(-4.0 * kPi * lq))) : 0.0;
     double lo = -40.0, hi = 1e5;
+    bool close = false;
     for (int it = 0; it < 200; ++it) {
-        double lt = log_gauss_tail(s);
-        double g = lt - lq;             // decreasing in s
+        const double lt = log_gauss_tail(s);
+        const double g = lt - lq;       // decreasing in s
         if (g > 0) lo = s; else hi = s;
-        double d = dlog_gauss_tail(s, lt);
+        const double d = dlog_gauss_tail(s, lt);
         double sn = s - g / d;
-        if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
-        if (std::fabs(sn - s) <= 1e-14 * std::fmax(1.0, std::fabs(s))) { s = sn; break; }
+        const bool newton = sn > lo && sn < hi;
+        if (close) {                    // the final step
+            if (newton) s = sn;
+            break;
+        }
+        if (!newton) sn = 0.5 * (lo + hi);
+        const double step = std::fabs(sn - s);
         s = sn;
+        if (step <= 1e-14 * std::fmax(1.0, std::fabs(s))) break;
+        close = newton && step <= 1e-7 * std::fmax(1.0, std::fabs(s));
     }
     return s;
 }

@@ -59,6 +59,22 @@ def test_host_thresholds_and_sigma_match_oracle(F):
         # powers above the noise mean (the inverse is ill-conditioned where Q -> 1)
         for pw in (H + 5.0, 2.0 * H + 20.0, 300.0, 5000.0):
             assert F.sigma_of(H, pw) == pytest.approx(O.candidate_sigma(H, pw), rel=1e-9, abs=1e-9)
+        # dense over the range candidates take (the Newton stopping rule included)
+        for pw in np.geomspace(H + 3.0, 1e6, 97):
+            assert F.sigma_of(H, pw) == pytest.approx(O.candidate_sigma(H, pw), rel=1e-9, abs=1e-9), (H, pw)
+
+
+def test_host_sigma_over_the_whole_range_matches_scipy(F):
+    """Significance of any sum, also far below the mean where Q -> 1 (lower tail
+    in log1p form), against scipy's regularised incomplete gamma and ndtri."""
+    from scipy import special
+    for H in (1, 2, 4, 8, 16, 32):
+        for S in np.geomspace(0.3, 1e5, 150):
+            Q, P = special.gammaincc(H, S), special.gammainc(H, S)
+            if min(Q, P) < 1e-290:
+                continue
+            ref = -special.ndtri(Q) if Q < 0.5 else special.ndtri(P)
+            assert F.sigma_of(H, S) == pytest.approx(ref, rel=1e-12, abs=1e-12), (H, S)
 
 
 def test_geometry_matches_oracle_and_rejects_bad_arguments(F):

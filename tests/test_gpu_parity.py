@@ -186,6 +186,20 @@ def test_search_chunked_workspace_matches_unchunked(fdas_gpu):
 
 # ----------------------------------------------------------------------------- edge cases
 
+def test_device_significance_equals_host_statistics(fdas_gpu):
+    """Record sigmas are computed on the device in FP64; they agree with the host
+    statistics (and so with the oracle's reading) for every stage."""
+    B, N, ts, zmax, dz, nh = 2, 1 << 14, 1e-3, 20.0, 2.0, 32
+    wl = synth.small_batch(B, N, ts, zmax, dz, nh, config=99, signals=2, amp_range=(0.3, 3.0))
+    x = _cuda(synth.generate(wl))
+    c = fdas_gpu.Plan(N, B, zmax, dz, nh).search(x, ts, sigma=2.5, cap=1 << 20)
+    assert len(c) > 1000 and len(set(c["harm"].tolist())) == 6
+    host = np.array([fdas_gpu.sigma_of(int(h), float(p)) for h, p in zip(c["harm"], c["power"])])
+    np.testing.assert_allclose(c["sigma"], host, rtol=1e-12, atol=1e-12)
+    for i in np.linspace(0, len(c) - 1, 25).astype(int):
+        assert c["sigma"][i] == pytest.approx(O.candidate_sigma(int(c["harm"][i]), float(c["power"][i])), rel=1e-9)
+
+
 def test_zero_series_give_no_candidates(fdas_gpu):
     N = 1 << 12
     x = np.zeros((2, N), dtype=np.float32)
