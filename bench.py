@@ -233,6 +233,8 @@ def main():
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("STATS_CSV", "OUT_MD", "COMMAND"),
                     help="write a markdown summary of a rocprofv3 kernel-stats CSV and exit")
+    ap.add_argument("--summary-title", default="",
+                    help="workload description for --stats-summary (default: the config's workload name)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND"),
                     help="summarise FETCH_SIZE/WRITE_SIZE runs into OUT_MD and profiles/traffic.json")
     ap.add_argument("--pmc-seg-len", type=int, default=2048,
@@ -240,9 +242,9 @@ def main():
     args = ap.parse_args()
     if args.stats_summary:
         csv_path, out_md, cmd = args.stats_summary
-        wl = _workload(args.config)
+        title = args.summary_title or _workload(args.config).name
         with open(out_md, "w") as fh:
-            fh.write(stats_summary(csv_path, f"Kernel time summary: {wl.name}", cmd))
+            fh.write(stats_summary(csv_path, f"Kernel time summary: {title}", cmd))
         return
     if args.pmc_summary:
         fcsv, wcsv, out_md, cmd = args.pmc_summary
@@ -651,6 +653,8 @@ def bench_pipeline(args):
     n_max = fb.nsamp // min(d for _, _, _, d in fb.plan)
     zmax, numharm = 50.0, 8
     plan = fdas.Plan(n_max, ndm, zmax, 2.0, numharm, autotune=1, graph=1, profile=0)
+    if args.tuning:
+        plan.load_tuning(args.tuning.replace(";", "\n"))
     dd = fdas.Plan(1 << 12, 1, 0.0, 2.0, 1, profile=1)
     trial_samples = sum(n * (fb.nsamp // d) for _, _, n, d in fb.plan)
     adds = sum(n * fb.nchan * (fb.nsamp // d) for _, _, n, d in fb.plan)
@@ -723,7 +727,8 @@ def bench_pipeline(args):
                      "launch_ms": 1e3 * k_dd},
         "cpu_baseline": cpu,
         "search": {"cells": cells, "ms": 1e3 * s_sec, "cells_per_s": cells / s_sec, "zmax": zmax,
-                   "numharm": numharm, "candidates": int(ncand)},
+                   "numharm": numharm, "candidates": int(ncand),
+                   "tuning": plan.tuning().strip().split("\n")},
         "end_to_end_ms": 1e3 * e_sec,
         "phases_ms": {k: round(v[0] / args.steps, 4) for k, v in ph.items()},
     }
