@@ -25,6 +25,10 @@
 
 namespace fdas {
 
+// Fourth word of a raw buffer resource on this GPU family (32-bit data
+// format; the base, stride 0 and the byte range come from the caller).
+static constexpr int kBufferRsrcWord3 = 0x00020000;
+
 template <int L>
 struct Corr {
     static constexpr int T = L / 8;          // threads per workgroup
@@ -227,20 +231,36 @@ __global__ __launch_bounds__(L / 8, FDAS_K4_MIN_WAVES) void k_corr_power(const f
 #pragma unroll
         for (int q = 0; q < 8; ++q) m0[q] = m1[q] = 0.0f;
     }
+    // Kernel spectra and plane rows go through buffer resources: a
+    // workgroup-uniform base and scalar offset plus the lane's fixed 32-bit
+    // offset, so loads and stores need no per-lane address arithmetic (the
+    // kernel is bound by VALU issue). The row resource covers the segment's
+    // 2 Lv columns.
+    const __amdgpu_buffer_rsrc_t bank_rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float2 *>(bank), (short)0, (int)(2 * g.NZ * L * (int)sizeof(float2)), kBufferRsrcWord3);
+    const int t_bank = t * (int)sizeof(float2);
+    const int t_row = 2 * t * (int)sizeof(float);
     for (int zi = z0; zi < z1; ++zi) {
-        float *row = out + (int64_t)zi * pitch;
+        const __amdgpu_buffer_rsrc_t row_rs = __builtin_amdgcn_make_buffer_rsrc(
+            out + (int64_t)zi * pitch, (short)0, 2 * g.Lv * (int)sizeof(float), kBufferRsrcWord3);
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            const float2 *Tz = bank + (int64_t)(2 * zi + p) * L;
             float2 v[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = cmul(S[q], Tz[t + q * T]);
+            for (int q = 0; q < 8; ++q) {
+                const int soff = ((2 * zi + p) * L + q * T) * (int)sizeof(float2);
+                v[q] = cmul(S[q], __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                                bank_rs, t_bank, soff, 0)));
+            }
             fft_block<L, 1>(v, lds, sel, tw, a);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int i = t + q * T;
                 const float pw = v[q].x * v[q].x + v[q].y * v[q].y;
-                if (i < g.Lv && ks + i < g.half) row[2 * i + p] = pw;
+                if (i < g.Lv && ks + i < g.half)
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, pw), row_rs,
+                                                          t_row + p * (int)sizeof(float),
+                                                          2 * q * T * (int)sizeof(float), 0);
                 if constexpr (PYR != 0) {
                     if (PYR == 2 || p == 0) m0[q] = fmaxf(m0[q], pw);
                     else m1[q] = fmaxf(m1[q], pw);
@@ -324,6 +344,9 @@ hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *sc
                              const float2 *bank, const CorrGeom &g, int nseries, float *plane,
                              int64_t pitch, int64_t series_stride, bmax_t *pyr,
                              int64_t pyr_series_stride, const RowBlocks &rb, hipStream_t st) {
+    // buffer resources take 32-bit byte ranges: the bank and a segment's row
+    if ((int64_t)2 * g.NZ * g.L * 8 > 0x7fffffffLL || (int64_t)2 * g.Lv * 4 > 0x7fffffffLL)
+        return hipErrorInvalidValue;
     if (nseries < 1 || g.nseg < 1 || g.Lv < 1 || (g.zgroups & (g.zgroups - 1)) || g.zgroups > 8 ||
         g.zgroups < 1 || (pitch & 1) || (pyr && (!rb.lo || !rb.of_row || rb.nblk < 1)))
         return hipErrorInvalidValue;
