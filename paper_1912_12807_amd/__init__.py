@@ -209,7 +209,9 @@ class Plan:
 
     def search(self, t, tsamp: float, zmax: float = None, dz: float = None, numharm: int = None,
                sigma: float = 6.0, cap: int = 1 << 16, stream=None, allow_trunc: bool = False):
-        """Candidates (structured numpy array, CAND_DTYPE) sorted by (series, harm, r_idx)."""
+        """Candidates (structured numpy array, CAND_DTYPE) sorted by (series, harm, r_idx).
+        With allow_trunc, (the first min(cap, total) records, total) instead, also
+        when the list was cut at cap."""
         t = _check_series(t)
         zmax = self.zmax if zmax is None else zmax
         dz = self.dz if dz is None else dz
@@ -220,8 +222,8 @@ class Plan:
                                   float(tsamp), float(zmax), float(dz), int(numharm), float(sigma),
                                   out.ctypes.data_as(ctypes.c_void_p), int(cap), ctypes.byref(n),
                                   _stream_handle(stream))
-        if st == FDAS_E_TRUNC and allow_trunc:
-            return out[:cap], int(n.value)
+        if allow_trunc and st in (FDAS_OK, FDAS_E_TRUNC):
+            return out[:min(int(cap), int(n.value))].copy(), int(n.value)
         if st != FDAS_OK:
             self._raise(st, "fdas_search")
         return out[:n.value].copy()

@@ -312,12 +312,37 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
                 const int kb = k0 + __builtin_ctzll(hm);
                 hm &= hm - 1;
                 const int zqa = blk_lo[kb] - Z, zqb = blk_lo[kb + 1] - 1 - Z;
+                // as the exhaustive sweep: fraction values stay in registers and
+                // are reloaded only when their (wave-uniform) row changes, the
+                // next row's loads issued before the current row is summed
+                const float *pz = pb + (int64_t)Z * pitch;     // row Zq = 0
+                float cur[NH];
+                int rowj[NH];
+#pragma unroll
+                for (int j = 1; j <= NH; ++j) {
+                    rowj[j - 1] = frac_row<NH>(zqa, j);
+                    cur[j - 1] = (need >> (j - 1)) & 1u ? pz[(int64_t)rowj[j - 1] * pitch + col[j - 1]] : 0.0f;
+                }
                 for (int zq = zqa; zq <= zqb; ++zq) {
-                    float P[NH], Ss[NS];
-                    gather<NH>(pb, pitch, Z, zq, col, need, P);
-                    stage_chain<NH>(P, Ss);
+                    float nxt[NH];
+#pragma unroll
+                    for (int j = 0; j < NH; ++j) nxt[j] = cur[j];
+                    if (zq < zqb) {
+#pragma unroll
+                        for (int j = 1; j <= NH; ++j) {
+                            const int r = frac_row<NH>(zq + 1, j);
+                            if (r != rowj[j - 1]) {
+                                rowj[j - 1] = r;
+                                nxt[j - 1] = (need >> (j - 1)) & 1u ? pz[(int64_t)r * pitch + col[j - 1]] : 0.0f;
+                            }
+                        }
+                    }
+                    float Ss[NS];
+                    stage_chain<NH>(cur, Ss);
 #pragma unroll
                     for (int s = 0; s < NS; ++s) mx[m][s] = fmaxf(mx[m][s], Ss[s]);
+#pragma unroll
+                    for (int j = 0; j < NH; ++j) cur[j] = nxt[j];
                 }
             }
         }

@@ -218,6 +218,8 @@ def test_truncation_reports_true_count(fdas_gpu):
     part, total = plan.search(_cuda(x), 1e-3, sigma=2.0, cap=17, allow_trunc=True)
     assert total == len(full)
     assert np.array_equal(part, full[:17])
+    whole, total = plan.search(_cuda(x), 1e-3, sigma=2.0, cap=1 << 16, allow_trunc=True)
+    assert total == len(full) and np.array_equal(whole, full)
 
 
 def test_invalid_arguments_return_status(fdas_gpu):
