@@ -226,7 +226,8 @@ def main():
                     help="time candidate launch parameters on the first search (during warmup)")
     ap.add_argument("--seg-len", type=int, default=0, help="plan option seg_len (0: the plan's choice)")
     ap.add_argument("--harm-block", type=int, default=0, help="plan option harm_block (0: default)")
-    ap.add_argument("--harm-pair", type=int, default=0, choices=(0, 1), help="plan option harm_pair")
+    ap.add_argument("--harm-pair", type=int, default=0, choices=(0, 1, 2),
+                    help="plan option harm_pair (0 automatic, 1 maxima per column, 2 per bin)")
     ap.add_argument("--tuning", default="",
                     help="launch parameters to preload, tuning lines separated by ';' (no tuning for those shapes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -342,9 +343,10 @@ def main():
         ser = wl.nseries / per_launch
         mp_ = (nr + 15) // 16 * 16
         if info["harm_blocks"]:
-            # bounded sums read the drift-block maxima once and write the stage maxima
+            # bounded sums read the drift-block maxima (2-byte halves) once and
+            # write the stage maxima (4-byte floats)
             ncols = nr // 2 if info["harm_pair"] else nr
-            byts = ser * (info["harm_blocks"] * ncols + NS * mp_) * 4.0
+            byts = ser * (info["harm_blocks"] * ncols * 2.0 + NS * mp_ * 4.0)
         else:
             byts = cells_launch * 4.0 + ser * NS * mp_ * 4.0
         achieved = byts / t_launch / 1e9

@@ -71,8 +71,9 @@ typedef struct {
     int32_t harm_bound;          /* 0: harmonic sums skip drift blocks whose block-maximum bound
                                     rules out a candidate (exact; default), 1: sum every cell */
     int32_t harm_block;          /* drift rows per bound block (0 = automatic) */
-    int32_t harm_pair;           /* 0: block maxima per bin, covering both half-bin columns
-                                    (default); 1: per column (tighter bound, twice the memory) */
+    int32_t harm_pair;           /* 0: automatic (per bin up to 8 harmonics, per column above);
+                                    1: block maxima per column (tighter bound, twice the memory);
+                                    2: per bin, covering both half-bin columns */
     int32_t autotune;            /* 1: on the first search of each shape (nsamp, zmax, numharm),
                                     time candidate seg_len / harm_block / harm_pair on that data
                                     and keep the fastest (results agree to FP32 rounding) */

@@ -48,6 +48,10 @@ struct Twiddles {
     float2 p2[7], p3[7], p4[Corr<L>::R4 > 1 ? Corr<L>::R4 - 1 : 1];
 };
 
+__device__ __forceinline__ float max_nonneg(float a, float b) {
+    return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+
 // a * exp(i pi K / 4) for a compile-time K
 template <int K>
 __device__ __forceinline__ float2 rot8(float2 a) {
@@ -162,22 +166,18 @@ __device__ __forceinline__ void fft_block(float2 *v, float *lds, int &sel, const
     }
 }
 
-// Minimum waves per SIMD requested from the register allocator (build-time tuning).
-#ifndef FDAS_K4_MIN_WAVES
-#define FDAS_K4_MIN_WAVES 1
-#endif
 
 // PYR: 0 no block maxima, 1 one maximum per column (half bin), 2 one per bin
 // (both parities).
 template <int L, int PYR>
-__global__ __launch_bounds__(L / 8, FDAS_K4_MIN_WAVES) void k_corr_power(const float2 *__restrict__ spec, int64_t spitch,
-                                                      const float *__restrict__ scale,
-                                                      const float2 *__restrict__ bank, CorrGeom g,
-                                                      int nseries, float *__restrict__ plane,
-                                                      int64_t pitch, int64_t sstride,
-                                                      bmax_t *__restrict__ pyr, int64_t psstride,
-                                                      const int32_t *__restrict__ blk_lo,
-                                                      const int32_t *__restrict__ blk_of_row) {
+__device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int64_t spitch,
+                                           const float *__restrict__ scale,
+                                           const float2 *__restrict__ bank, CorrGeom g,
+                                           int nseries, float *__restrict__ plane,
+                                           int64_t pitch, int64_t sstride,
+                                           bmax_t *__restrict__ pyr, int64_t psstride,
+                                           const int32_t *__restrict__ blk_lo,
+                                           const int32_t *__restrict__ blk_of_row) {
     constexpr int T = Corr<L>::T;
     __shared__ float lds[4 * Corr<L>::LDSZ];
     const int t = threadIdx.x;
@@ -256,14 +256,18 @@ __global__ __launch_bounds__(L / 8, FDAS_K4_MIN_WAVES) void k_corr_power(const f
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int i = t + q * T;
-                const float pw = v[q].x * v[q].x + v[q].y * v[q].y;
+                const float pw = __fmaf_rn(v[q].x, v[q].x, __fmul_rn(v[q].y, v[q].y));
                 if (i < g.Lv && ks + i < g.half)
                     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, pw), row_rs,
                                                           t_row + p * (int)sizeof(float),
                                                           2 * q * T * (int)sizeof(float), 0);
-                if constexpr (PYR != 0) {
-                    if (PYR == 2 || p == 0) m0[q] = fmaxf(m0[q], pw);
-                    else m1[q] = fmaxf(m1[q], pw);
+                if constexpr (PYR == 2) {
+                    m0[q] = fmaxf(m0[q], pw);     // both parities: fused into 3-input maxima
+                } else if constexpr (PYR == 1) {
+                    // powers are >= +0, so their bit patterns order like their
+                    // values: an integer maximum needs no NaN canonicalisation
+                    if (p == 0) m0[q] = max_nonneg(m0[q], pw);
+                    else m1[q] = max_nonneg(m1[q], pw);
                 }
             }
         }
@@ -289,6 +293,30 @@ __global__ __launch_bounds__(L / 8, FDAS_K4_MIN_WAVES) void k_corr_power(const f
         }
     }
 }
+
+#define FDAS_K4_PARAMS                                                                                \
+    const float2 *__restrict__ spec, int64_t spitch, const float *__restrict__ scale,                  \
+        const float2 *__restrict__ bank, CorrGeom g, int nseries, float *__restrict__ plane,           \
+        int64_t pitch, int64_t sstride, bmax_t *__restrict__ pyr, int64_t psstride,                    \
+        const int32_t *__restrict__ blk_lo, const int32_t *__restrict__ blk_of_row
+#define FDAS_K4_ARGS spec, spitch, scale, bank, g, nseries, plane, pitch, sstride, pyr, psstride, blk_lo, blk_of_row
+
+template <int L, int PYR>
+__global__ __launch_bounds__(L / 8) void k_corr_power(FDAS_K4_PARAMS) {
+    corr_power<L, PYR>(FDAS_K4_ARGS);
+}
+
+// Per-column maxima keep two running maxima per point: at the 4 waves per SIMD
+// that LDS allows, the compiler then has so few registers left that it
+// serialises the kernel-spectrum loads; 3 waves with the loads in flight
+// together are faster.
+template <int L>
+__global__ __launch_bounds__(L / 8) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_corr_power_cols(
+    FDAS_K4_PARAMS) {
+    corr_power<L, 1>(FDAS_K4_ARGS);
+}
+#undef FDAS_K4_PARAMS
+#undef FDAS_K4_ARGS
 
 void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int32_t> &of_row) {
     lo.clear();
@@ -331,12 +359,12 @@ static void launch_l(const float2 *spec, int64_t spitch, const float *scale, con
                      const CorrGeom &g, int nseries, float *plane, int64_t pitch, int64_t sstride,
                      bmax_t *pyr, int64_t psstride, const RowBlocks &rb, int64_t nwg, hipStream_t st) {
     const int mode = pyr ? (rb.pair ? 2 : 1) : 0;
-#define FDAS_K4(M)                                                                                  \
-    hipLaunchKernelGGL((k_corr_power<L, M>), dim3((unsigned)nwg), dim3(L / 8), 0, st, spec, spitch, \
-                       scale, bank, g, nseries, plane, pitch, sstride, pyr, psstride, rb.lo, rb.of_row)
-    if (mode == 0) FDAS_K4(0);
-    else if (mode == 1) FDAS_K4(1);
-    else FDAS_K4(2);
+#define FDAS_K4(KERNEL)                                                                             \
+    hipLaunchKernelGGL(KERNEL, dim3((unsigned)nwg), dim3(L / 8), 0, st, spec, spitch, scale, bank, g, \
+                       nseries, plane, pitch, sstride, pyr, psstride, rb.lo, rb.of_row)
+    if (mode == 0) FDAS_K4((k_corr_power<L, 0>));
+    else if (mode == 1) FDAS_K4((k_corr_power_cols<L>));
+    else FDAS_K4((k_corr_power<L, 2>));
 #undef FDAS_K4
 }
 
