@@ -331,8 +331,8 @@ fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out);
  * the summed device milliseconds and launches[i] the number of timed
  * launches of phase i since the last reset (both arrays hold FDAS_NPHASES
  * entries, either may be NULL). Phases: 0 real FFT, 1 normalisation,
- * 2 power plane, 3 harmonic sums, 4 compaction, 5 drift argmax and FP64
- * significance of the records, 6 copy-out,
+ * 2 power plane, 3 harmonic sums (with the maximising drift), 4 compaction,
+ * 5 FP64 significance of the records, 6 copy-out,
  * 7 refinement, 8 dedispersion.
  * reset != 0 clears the totals after reading. */
 #define FDAS_NPHASES 9

@@ -30,7 +30,7 @@ EXPORTED = (
     "fdas_refine_eval", "fdas_refine_grad", "fdas_refine", "fdas_refine_window", "fdas_dedisperse",
     "fdas_sift",
 )
-PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "argmax", "copyout", "refine", "dedisperse")
+PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "sigma", "copyout", "refine", "dedisperse")
 
 
 class PlanOpts(ctypes.Structure):

@@ -7,10 +7,10 @@
 //   K1 real FFT -> K2 median normalisation (or a fixed scale)
 //   then per chunk of series (sized to the plane workspace):
 //   K4 power plane + drift-block maxima -> K5 harmonic sums -> K6 ordered
-//   compaction -> drift argmax.
-// The record count and the records are then copied to pinned host memory,
-// where the FP64 significance and physical units are attached (the candidate
-// list of the paper's Section 2, step 5).
+//   compaction (with the drift argmax from the sums) -> significance.
+// The record count and the records (with their FP64 significance) are then
+// copied to pinned host memory, where physical units are attached (the
+// candidate list of the paper's Section 2, step 5).
 #include "fdas_internal.h"
 
 #include <algorithm>
@@ -153,6 +153,7 @@ struct fdas_plan_s {
     float *d_plane = nullptr;
     int64_t plane_cap = 0;      // floats
     float *d_maxv = nullptr;
+    int16_t *d_zarg = nullptr;  // maximising Zq of each stage maximum (maxv_cap entries)
     int64_t maxv_cap = 0;       // floats
     int32_t *d_counts = nullptr;
     int64_t *d_offsets = nullptr;
@@ -494,7 +495,7 @@ fdas_status run_spectrum(fdas_plan p, const float *x, const int64_t *offs, int64
     return FDAS_OK;
 }
 
-// K4 [+ K5 + K6 + argmax] for the nb series whose spectra are in batch slots
+// K4 [+ K5 + K6 + significance] for the nb series whose spectra are in batch slots
 // vbase..., in chunks that the workspace holds. timing_only stops after K5
 // (autotuner).
 fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const LaunchCfg &cfg,
@@ -527,21 +528,19 @@ fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
         e = p->begin(st);
         if (bounded) {
             HIPTRY(p, launch_harmsum_bounded(p->d_plane, pitch, sstride, p->d_pyr, psstride, rb, g.NR, g.rlo,
-                                             g.Z, numharm, n, p->d_thr, p->d_maxv, mpitch, st));
+                                             g.Z, numharm, n, p->d_thr, p->d_maxv, p->d_zarg, mpitch, st));
         } else {
             const int order = p->opts.harm_order ? p->opts.harm_order : 1;
             HIPTRY(p, launch_harmsum(p->d_plane, pitch, sstride, g.NR, g.rlo, g.Z, numharm, n, p->d_maxv,
-                                     mpitch, order, st));
+                                     p->d_zarg, mpitch, order, st));
         }
         p->end(3, e, st);
         if (timing_only) continue;
         e = p->begin(st);
-        HIPTRY(p, launch_compact(p->d_maxv, (int64_t)n * NS * mpitch, mpitch, NS, vbase + b0, p->d_thr,
+        HIPTRY(p, launch_compact(p->d_maxv, p->d_zarg, (int64_t)n * NS * mpitch, mpitch, NS, vbase + b0, p->d_thr,
                                  p->d_counts, p->d_offsets, p->d_state, p->d_rec, p->rec_cap, st));
         p->end(4, e, st);
         e = p->begin(st);
-        HIPTRY(p, launch_argmax(p->d_plane, pitch, sstride, g.rlo, g.Z, numharm, vbase + b0, p->d_rec,
-                                p->d_state, p->rec_cap, st));
         HIPTRY(p, launch_cand_sigma(p->d_rec, p->d_state, p->rec_cap, st));
         p->end(5, e, st);
     }
@@ -918,7 +917,7 @@ void fdas_plan_destroy(fdas_plan p) {
     for (auto &t : p->tables) (void)hipFree(t.d);
     for (auto &t : p->ltabs) (void)hipFree(t.second.first);
     void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_med, p->d_thr, p->d_state, p->d_offs,
-                   p->d_plane, p->d_maxv, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow, p->d_dd[0], p->d_dd[1], p->d_delays, p->d_csum, p->d_cpad, p->d_lmed};
+                   p->d_plane, p->d_maxv, p->d_zarg, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow, p->d_dd[0], p->d_dd[1], p->d_delays, p->d_csum, p->d_cpad, p->d_lmed};
     for (void *q : dev)
         if (q) (void)hipFree(q);
     for (auto &t : p->ev_pending) {
@@ -1010,6 +1009,7 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     const int NS = nstages_of(numharm);
     p->maxv_cap = chunk * NS * round_up(max_nsamp, 16);
     if ((s = dalloc(p, &p->d_maxv, p->maxv_cap, "stage maxima")) != FDAS_OK) return bail(s);
+    if ((s = dalloc(p, &p->d_zarg, p->maxv_cap, "stage maxima drift indices")) != FDAS_OK) return bail(s);
     p->nblk_cap = compact_blocks(p->maxv_cap);
     if ((s = dalloc(p, &p->d_counts, p->nblk_cap, "compaction counts")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_offsets, p->nblk_cap, "compaction offsets")) != FDAS_OK) return bail(s);
@@ -1420,20 +1420,18 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
             if (bounded) {
                 HIPTRY(p, launch_block_max(pl, g.NR, sstride, g.NR, rb, nb, p->d_pyr, psstride, st));
                 HIPTRY(p, launch_harmsum_bounded(pl, g.NR, sstride, p->d_pyr, psstride, rb, g.NR, g.rlo, g.Z,
-                                                 numharm, nb, p->d_thr, p->d_maxv, mpitch, st));
+                                                 numharm, nb, p->d_thr, p->d_maxv, p->d_zarg, mpitch, st));
             } else {
                 const int order = p->opts.harm_order ? p->opts.harm_order : 1;
-                HIPTRY(p, launch_harmsum(pl, g.NR, sstride, g.NR, g.rlo, g.Z, numharm, nb, p->d_maxv, mpitch,
-                                         order, st));
+                HIPTRY(p, launch_harmsum(pl, g.NR, sstride, g.NR, g.rlo, g.Z, numharm, nb, p->d_maxv, p->d_zarg,
+                                         mpitch, order, st));
             }
             p->end(3, e, st);
             e = p->begin(st);
-            HIPTRY(p, launch_compact(p->d_maxv, (int64_t)nb * NS * mpitch, mpitch, NS, b0, p->d_thr, p->d_counts,
-                                     p->d_offsets, p->d_state, p->d_rec, p->rec_cap, st));
+            HIPTRY(p, launch_compact(p->d_maxv, p->d_zarg, (int64_t)nb * NS * mpitch, mpitch, NS, b0, p->d_thr,
+                                     p->d_counts, p->d_offsets, p->d_state, p->d_rec, p->rec_cap, st));
             p->end(4, e, st);
             e = p->begin(st);
-            HIPTRY(p, launch_argmax(pl, g.NR, sstride, g.rlo, g.Z, numharm, b0, p->d_rec, p->d_state, p->rec_cap,
-                                    st));
             HIPTRY(p, launch_cand_sigma(p->d_rec, p->d_state, p->rec_cap, st));
             p->end(5, e, st);
         }

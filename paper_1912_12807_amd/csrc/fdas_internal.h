@@ -39,7 +39,7 @@ struct DevCand {
     int32_t b;       // series within the batch
     int32_t s;       // stage index: H = 1 << s
     int32_t c;       // column: R = c + 2 rlo
-    int32_t zq;      // smallest maximising z index (filled by the argmax kernel)
+    int32_t zq;      // smallest maximising z index
     float power;     // M_H(R)
     int32_t pad;
     double sigma;    // significance of power at stage H (filled by launch_cand_sigma)
@@ -121,12 +121,13 @@ hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *sc
                              int64_t pyr_series_stride, const RowBlocks &rb, hipStream_t st);
 
 // K5: harmonic sums and maxima over z for every column and stage.
-// maxv: [nseries][nstages][mpitch] (zero where a stage is not searched).
+// maxv: [nseries][nstages][mpitch] (zero where a stage is not searched);
+// zarg, same layout: the smallest Zq reaching the maximum (|Zq| <= 32767).
 // order: 1 each XCD sweeps a contiguous run of tiles, 2 all XCDs sweep the
 // tiles in launch order, 3 as 2 but in two launches over the drift halves
 // (Zq <= 0, then Zq > 0 merged), which halves the live plane per series.
 hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
-                          int64_t rlo, int Z, int numharm, int nseries, float *maxv,
+                          int64_t rlo, int Z, int numharm, int nseries, float *maxv, int16_t *zarg,
                           int64_t mpitch, int order, hipStream_t st);
 
 // Block maxima of a caller-supplied plane (what K4 writes alongside its plane).
@@ -137,30 +138,28 @@ hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_st
 // K5 with block bounds: per column and drift block, the stage chain over the
 // block maxima bounds every exact stage sum of the block from above (FP32
 // addition is monotone); only blocks where some searched stage's bound
-// exceeds its threshold are summed exactly. maxv is exact wherever it exceeds
-// the threshold (elsewhere it only stays at or below it), so the candidates
-// equal those of launch_harmsum bit for bit.
+// exceeds its threshold are summed exactly. maxv (and zarg) is exact wherever
+// it exceeds the threshold (elsewhere it only stays at or below it), so the
+// candidates equal those of launch_harmsum bit for bit.
 hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
                                   const bmax_t *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
                                   int64_t NR, int64_t rlo, int Z, int numharm, int nseries,
-                                  const float *thr_dev, float *maxv, int64_t mpitch, hipStream_t st);
+                                  const float *thr_dev, float *maxv, int16_t *zarg, int64_t mpitch,
+                                  hipStream_t st);
 
-// K6: ordered compaction of maxv > thr[stage] into records in (b, s, c) order.
+// K6: ordered compaction of maxv > thr[stage] into records in (b, s, c) order,
+// with the drift index from zarg.
 // The batch may be processed in series chunks: state[0] (device int64) is the
 // running record count over the chunks done so far, and after the call
 // state[1] holds this chunk's first record index. Records at index >= cap are
 // counted but not written. counts/offsets: scratch of compact_blocks() entries.
 int64_t compact_blocks(int64_t nelem);
-hipError_t launch_compact(const float *maxv, int64_t nelem, int64_t mpitch, int nstages,
-                          int b0, const float *thr_dev, int32_t *counts, int64_t *offsets,
+hipError_t launch_compact(const float *maxv, const int16_t *zarg, int64_t nelem, int64_t mpitch,
+                          int nstages, int b0, const float *thr_dev, int32_t *counts, int64_t *offsets,
                           int64_t *state, DevCand *out, int64_t cap, hipStream_t st);
 
-// Smallest maximising z index of this chunk's records [state[1], min(state[0], cap)),
-// recomputing the stage sums from the chunk's plane (series b0 is plane row 0).
-hipError_t launch_argmax(const float *plane, int64_t pitch, int64_t series_stride, int64_t rlo,
-                         int Z, int numharm, int b0, DevCand *rec, const int64_t *state,
-                         int64_t cap, hipStream_t st);
-// FP64 significance of the same records (the host statistics' arithmetic).
+// FP64 significance of this chunk's records [state[1], min(state[0], cap))
+// (the host statistics' arithmetic).
 hipError_t launch_cand_sigma(DevCand *rec, const int64_t *state, int64_t cap, hipStream_t st);
 
 // K0: dedispersion. x: time-major uint8 [nsamp][nchan]; y: channel-major float

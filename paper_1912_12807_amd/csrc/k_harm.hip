@@ -85,8 +85,8 @@ __device__ __forceinline__ int frac_row(int zq, int j) {
 template <int NH>
 __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane, int64_t pitch,
                                                  int64_t sstride, int64_t NR, int64_t rlo, int Z,
-                                                 float *__restrict__ maxv, int64_t mpitch,
-                                                 int64_t tiles_per_series, int64_t total_tiles,
+                                                 float *__restrict__ maxv, int16_t *__restrict__ zarg,
+                                                 int64_t mpitch, int64_t tiles_per_series, int64_t total_tiles,
                                                  int xcd_runs, int zq_lo, int zq_hi, int merge) {
     constexpr int NS = Stages<NH>::NS;
     const int64_t w = blockIdx.x;
@@ -100,22 +100,35 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
     const int64_t c = (g - (int64_t)b * tiles_per_series) * 256 + threadIdx.x;
     if (c >= mpitch) return;
     float *mo = maxv + (int64_t)b * NS * mpitch + c;
+    int16_t *za = zarg + (int64_t)b * NS * mpitch + c;
     if (c >= NR) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) mo[s * mpitch] = 0.0f;
+        for (int s = 0; s < NS; ++s) {
+            mo[s * mpitch] = 0.0f;
+            za[s * mpitch] = 0;
+        }
         return;
     }
     const int64_t R = c + 2 * rlo;
     int64_t col[NH];
     const uint32_t need = column_offsets<NH>(R, rlo, col);
     const float *pb = plane + (int64_t)b * sstride + (int64_t)Z * pitch;   // row Zq = 0
+    // maxima and their smallest maximising Zq (the sweep runs upward in Zq and
+    // a later row replaces the maximum only when strictly larger)
     float mx[NS];
+    int az[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) mx[s] = 0.0f;
+    for (int s = 0; s < NS; ++s) {
+        mx[s] = 0.0f;
+        az[s] = zq_lo;
+    }
 
     if (merge) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) mx[s] = mo[s * mpitch];
+        for (int s = 0; s < NS; ++s) {
+            mx[s] = mo[s * mpitch];
+            az[s] = za[s * mpitch];
+        }
     }
     float cur[NH];
     int row[NH];
@@ -141,12 +154,21 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
         float Ss[NS];
         stage_chain<NH>(cur, Ss);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) mx[s] = fmaxf(mx[s], Ss[s]);
+        for (int s = 0; s < NS; ++s) {
+            if (Ss[s] > mx[s]) {
+                mx[s] = Ss[s];
+                az[s] = zq;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < NH; ++j) cur[j] = nxt[j];
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) mo[s * mpitch] = (R >= 2 * rlo * (1 << s)) ? mx[s] : 0.0f;
+    for (int s = 0; s < NS; ++s) {
+        const bool on = R >= 2 * rlo * (1 << s);
+        mo[s * mpitch] = on ? mx[s] : 0.0f;
+        za[s * mpitch] = (int16_t)(on ? az[s] : 0);
+    }
 }
 
 // Bounded variant: lane = column R, loop over drift blocks. For fraction j the
@@ -184,9 +206,9 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
                                                     const int32_t *__restrict__ frange, int nblk,
                                                     int64_t NR, int64_t rlo, int Z,
                                                     const float *__restrict__ thr,
-                                                    float *__restrict__ maxv, int64_t mpitch,
-                                                    int64_t tiles_per_series, int64_t total_tiles,
-                                                    int pair, int nseries) {
+                                                    float *__restrict__ maxv, int16_t *__restrict__ zarg,
+                                                    int64_t mpitch, int64_t tiles_per_series,
+                                                    int64_t total_tiles, int pair, int nseries) {
     constexpr int NS = Stages<NH>::NS;
     constexpr int SB = BoundCfg<NH>::SB;
 
@@ -206,8 +228,12 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         for (int m = 0; m < SB; ++m) {
             if (b0 + m >= nseries) break;
             float *mo = maxv + (int64_t)(b0 + m) * NS * mpitch + c;
+            int16_t *za = zarg + (int64_t)(b0 + m) * NS * mpitch + c;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) mo[s * mpitch] = 0.0f;
+            for (int s = 0; s < NS; ++s) {
+                mo[s * mpitch] = 0.0f;
+                za[s * mpitch] = 0;
+            }
         }
         return;
     }
@@ -239,12 +265,22 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         th[s] = thr[s];
         valid[s] = R >= 2 * rlo * (1 << s);
     }
+    // Exact maxima over the hot blocks and their smallest maximising Zq: a
+    // column's maximum above threshold lies in a hot block (every other block's
+    // sums are at or below its bound, itself at or below the threshold), and
+    // hot blocks are summed in increasing Zq with strictly larger values only
+    // replacing the maximum. The Zq of two stages share a register as 16-bit
+    // halves (the block tests need the registers).
+    constexpr int NP = (NS + 1) / 2;
     float mx[SB][NS];
+    uint32_t azp[SB][NP];
 #pragma unroll
-    for (int m = 0; m < SB; ++m)
+    for (int m = 0; m < SB; ++m) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) mx[m][s] = 0.0f;
-
+#pragma unroll
+        for (int h = 0; h < NP; ++h) azp[m][h] = 0u;
+    }
     for (int k0 = 0; k0 < nblk; k0 += 64) {
         // pass 1: per series, a wave-uniform mask of the blocks some lane cannot rule out
         uint64_t hotmask[SB];
@@ -340,7 +376,13 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
                     float Ss[NS];
                     stage_chain<NH>(cur, Ss);
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) mx[m][s] = fmaxf(mx[m][s], Ss[s]);
+                    for (int s = 0; s < NS; ++s) {
+                        if (Ss[s] > mx[m][s]) {
+                            mx[m][s] = Ss[s];
+                            const uint32_t sh = 16u * (s & 1);
+                            azp[m][s >> 1] = (azp[m][s >> 1] & ~(0xffffu << sh)) | ((uint32_t)(uint16_t)zq << sh);
+                        }
+                    }
 #pragma unroll
                     for (int j = 0; j < NH; ++j) cur[j] = nxt[j];
                 }
@@ -351,45 +393,12 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
     for (int m = 0; m < SB; ++m) {
         if (b0 + m >= nseries) break;
         float *mo = maxv + (int64_t)(b0 + m) * NS * mpitch + c;
+        int16_t *za = zarg + (int64_t)(b0 + m) * NS * mpitch + c;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) mo[s * mpitch] = valid[s] ? mx[m][s] : 0.0f;
-    }
-}
-
-template <int NH>
-__global__ __launch_bounds__(256) void k_argmax(const float *__restrict__ plane, int64_t pitch,
-                                                int64_t sstride, int64_t rlo, int Z, int b0,
-                                                DevCand *__restrict__ rec,
-                                                const int64_t *__restrict__ state, int64_t cap) {
-    constexpr int NS = Stages<NH>::NS;
-    const int64_t begin = state[1];
-    const int64_t end = state[0] < cap ? state[0] : cap;
-    const int lane = threadIdx.x & 63;
-    const int64_t gw = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t i = begin + gw; i < end; i += nw) {
-        const DevCand r = rec[i];
-        const int64_t R = r.c + 2 * rlo;
-        int64_t col[NH];
-        const uint32_t need = column_offsets<NH>(R, rlo, col);
-        const float *pb = plane + (int64_t)(r.b - b0) * sstride;
-        int best = INT_MAX;
-        for (int zq = -Z + lane; zq <= Z; zq += 64) {
-            float P[NH], Ss[NS];
-            gather<NH>(pb, pitch, Z, zq, col, need, P);
-            stage_chain<NH>(P, Ss);
-            float v = Ss[0];
-#pragma unroll
-            for (int s = 1; s < NS; ++s)
-                if (s == r.s) v = Ss[s];
-            if (v == r.power && zq < best) best = zq;
+        for (int s = 0; s < NS; ++s) {
+            mo[s * mpitch] = valid[s] ? mx[m][s] : 0.0f;
+            za[s * mpitch] = (int16_t)(valid[s] ? (azp[m][s >> 1] >> (16u * (s & 1))) & 0xffffu : 0u);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const int o = __shfl_xor(best, off, 64);
-            best = o < best ? o : best;
-        }
-        if (lane == 0) rec[i].zq = best;
     }
 }
 
@@ -455,7 +464,8 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *tmp, int &total)
 }
 
 template <bool SCATTER>
-__global__ __launch_bounds__(256) void k_compact(const float *__restrict__ maxv, int64_t nelem,
+__global__ __launch_bounds__(256) void k_compact(const float *__restrict__ maxv,
+                                                 const int16_t *__restrict__ zarg, int64_t nelem,
                                                  int64_t mpitch, int ns, int b0,
                                                  const float *__restrict__ thr,
                                                  int32_t *__restrict__ counts,
@@ -502,7 +512,7 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ maxv,
                 d.b = b0 + row / ns;
                 d.s = row % ns;
                 d.c = (int32_t)(c0 + i);
-                d.zq = INT_MAX;
+                d.zq = zarg[e0 + i];
                 d.power = v[i];
                 d.pad = 0;
                 d.sigma = 0.0;
@@ -547,8 +557,8 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict_
 
 template <int NH>
 static void launch_harm_nh(const float *plane, int64_t pitch, int64_t sstride, int64_t NR,
-                           int64_t rlo, int Z, int nseries, float *maxv, int64_t mpitch, int order,
-                           hipStream_t st) {
+                           int64_t rlo, int Z, int nseries, float *maxv, int16_t *zarg, int64_t mpitch,
+                           int order, hipStream_t st) {
     const int64_t tps = (mpitch + 255) / 256;
     const int64_t total = tps * nseries;
     const int64_t nwg = 8 * ((total + 7) / 8);
@@ -556,28 +566,28 @@ static void launch_harm_nh(const float *plane, int64_t pitch, int64_t sstride, i
     if (order == 3 && Z > 0) {
         // negative drift half, then the positive half merged into the same maxima
         hipLaunchKernelGGL(k_harmsum<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
-                           NR, rlo, Z, maxv, mpitch, tps, total, 0, -Z, 0, 0);
+                           NR, rlo, Z, maxv, zarg, mpitch, tps, total, 0, -Z, 0, 0);
         hipLaunchKernelGGL(k_harmsum<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
-                           NR, rlo, Z, maxv, mpitch, tps, total, 0, 1, Z, 1);
+                           NR, rlo, Z, maxv, zarg, mpitch, tps, total, 0, 1, Z, 1);
     } else {
         hipLaunchKernelGGL(k_harmsum<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
-                           NR, rlo, Z, maxv, mpitch, tps, total, xcd_runs, -Z, Z, 0);
+                           NR, rlo, Z, maxv, zarg, mpitch, tps, total, xcd_runs, -Z, Z, 0);
     }
 }
 
 hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
-                          int64_t rlo, int Z, int numharm, int nseries, float *maxv,
+                          int64_t rlo, int Z, int numharm, int nseries, float *maxv, int16_t *zarg,
                           int64_t mpitch, int order, hipStream_t st) {
     if (nseries < 1 || mpitch < NR || (mpitch & 15) || (mpitch + 255) / 256 * nseries > 0x7ffffff0LL ||
-        order < 1 || order > 3)
+        order < 1 || order > 3 || !zarg || Z > 32767)
         return hipErrorInvalidValue;
     switch (numharm) {
-    case 1: launch_harm_nh<1>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
-    case 2: launch_harm_nh<2>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
-    case 4: launch_harm_nh<4>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
-    case 8: launch_harm_nh<8>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
-    case 16: launch_harm_nh<16>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
-    case 32: launch_harm_nh<32>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, mpitch, order, st); break;
+    case 1: launch_harm_nh<1>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, zarg, mpitch, order, st); break;
+    case 2: launch_harm_nh<2>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, zarg, mpitch, order, st); break;
+    case 4: launch_harm_nh<4>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, zarg, mpitch, order, st); break;
+    case 8: launch_harm_nh<8>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, zarg, mpitch, order, st); break;
+    case 16: launch_harm_nh<16>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, zarg, mpitch, order, st); break;
+    case 32: launch_harm_nh<32>(plane, pitch, series_stride, NR, rlo, Z, nseries, maxv, zarg, mpitch, order, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -586,26 +596,29 @@ hipError_t launch_harmsum(const float *plane, int64_t pitch, int64_t series_stri
 template <int NH>
 static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, const bmax_t *pyr,
                             int64_t psstride, const RowBlocks &rb, int64_t NR, int64_t rlo, int Z,
-                            int nseries, const float *thr, float *maxv, int64_t mpitch, hipStream_t st) {
+                            int nseries, const float *thr, float *maxv, int16_t *zarg, int64_t mpitch,
+                            hipStream_t st) {
     const int64_t tps = (mpitch + 255) / 256;
     const int64_t groups = (nseries + BoundCfg<NH>::SB - 1) / BoundCfg<NH>::SB;
     const int64_t total = tps * groups;
     const int64_t nwg = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL(k_harm_bound<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
-                       pyr, psstride, rb.lo, rb.frange, rb.nblk, NR, rlo, Z, thr, maxv, mpitch, tps, total,
-                       rb.pair ? 1 : 0, nseries);
+                       pyr, psstride, rb.lo, rb.frange, rb.nblk, NR, rlo, Z, thr, maxv, zarg, mpitch, tps,
+                       total, rb.pair ? 1 : 0, nseries);
 }
 
 hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
                                   const bmax_t *pyr, int64_t pyr_series_stride, const RowBlocks &rb,
                                   int64_t NR, int64_t rlo, int Z, int numharm, int nseries,
-                                  const float *thr_dev, float *maxv, int64_t mpitch, hipStream_t st) {
+                                  const float *thr_dev, float *maxv, int16_t *zarg, int64_t mpitch,
+                                  hipStream_t st) {
     // block-maxima offsets within one series are 32-bit in the kernel
     if (nseries < 1 || mpitch < NR || (mpitch & 15) || (mpitch + 255) / 256 * nseries > 0x7ffffff0LL ||
         !pyr || !rb.lo || !rb.frange || rb.nblk < 1 || rb.frange_nh != numharm ||
-        bounded_table_bytes(rb.nblk, numharm) > kBoundTableMax || pyr_series_stride > kMaxPyrSeriesStride)
+        bounded_table_bytes(rb.nblk, numharm) > kBoundTableMax || pyr_series_stride > kMaxPyrSeriesStride ||
+        !zarg || Z > 32767)
         return hipErrorInvalidValue;
-#define FDAS_BOUND(NHV) launch_bound_nh<NHV>(plane, pitch, series_stride, pyr, pyr_series_stride, rb, NR, rlo, Z, nseries, thr_dev, maxv, mpitch, st)
+#define FDAS_BOUND(NHV) launch_bound_nh<NHV>(plane, pitch, series_stride, pyr, pyr_series_stride, rb, NR, rlo, Z, nseries, thr_dev, maxv, zarg, mpitch, st)
     switch (numharm) {
     case 1: FDAS_BOUND(1); break;
     case 2: FDAS_BOUND(2); break;
@@ -630,40 +643,18 @@ hipError_t launch_zero_state(int64_t *state, hipStream_t st) {
 
 int64_t compact_blocks(int64_t nelem) { return (nelem + kCB - 1) / kCB; }
 
-hipError_t launch_compact(const float *maxv, int64_t nelem, int64_t mpitch, int nstages, int b0,
+hipError_t launch_compact(const float *maxv, const int16_t *zarg, int64_t nelem, int64_t mpitch, int nstages,
+                          int b0,
                           const float *thr_dev, int32_t *counts, int64_t *offsets, int64_t *state,
                           DevCand *out, int64_t cap, hipStream_t st) {
     if ((mpitch & 15) || nelem % mpitch) return hipErrorInvalidValue;
     const int64_t nblk = compact_blocks(nelem);
     if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_compact<false>, dim3((unsigned)nblk), dim3(256), 0, st, maxv, nelem, mpitch,
+    hipLaunchKernelGGL(k_compact<false>, dim3((unsigned)nblk), dim3(256), 0, st, maxv, zarg, nelem, mpitch,
                        nstages, b0, thr_dev, counts, offsets, out, cap);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, counts, nblk, offsets, state);
-    hipLaunchKernelGGL(k_compact<true>, dim3((unsigned)nblk), dim3(256), 0, st, maxv, nelem, mpitch,
+    hipLaunchKernelGGL(k_compact<true>, dim3((unsigned)nblk), dim3(256), 0, st, maxv, zarg, nelem, mpitch,
                        nstages, b0, thr_dev, counts, offsets, out, cap);
-    return hipGetLastError();
-}
-
-template <int NH>
-static void launch_argmax_nh(const float *plane, int64_t pitch, int64_t sstride, int64_t rlo,
-                             int Z, int b0, DevCand *rec, const int64_t *state, int64_t cap,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_argmax<NH>, dim3(1024), dim3(256), 0, st, plane, pitch, sstride, rlo, Z, b0,
-                       rec, state, cap);
-}
-
-hipError_t launch_argmax(const float *plane, int64_t pitch, int64_t series_stride, int64_t rlo,
-                         int Z, int numharm, int b0, DevCand *rec, const int64_t *state,
-                         int64_t cap, hipStream_t st) {
-    switch (numharm) {
-    case 1: launch_argmax_nh<1>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
-    case 2: launch_argmax_nh<2>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
-    case 4: launch_argmax_nh<4>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
-    case 8: launch_argmax_nh<8>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
-    case 16: launch_argmax_nh<16>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
-    case 32: launch_argmax_nh<32>(plane, pitch, series_stride, rlo, Z, b0, rec, state, cap, st); break;
-    default: return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
