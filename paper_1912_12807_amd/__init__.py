@@ -178,6 +178,7 @@ class Plan:
     """A device plan: template bank and workspace for series up to max_nsamp."""
 
     def __init__(self, max_nsamp: int, max_series: int, zmax: float, dz: float, numharm: int, **opts):
+        self._out = None
         self.lib = load()
         self.opts = default_opts(**opts)
         self.handle = ctypes.c_void_p()
@@ -207,6 +208,16 @@ class Plan:
         return geometry(nsamp, tsamp, self.zmax if zmax is None else zmax,
                         self.dz if dz is None else dz, self.opts)
 
+    def _staging(self, cap: int):
+        """Reused host buffer for the library's records (the caller gets copies):
+        a fresh buffer per call would page-fault its written part every time."""
+        cap = int(cap)
+        if cap < 0:
+            raise ValueError("cap must be >= 0")
+        if self._out is None or len(self._out) < cap:
+            self._out = np.zeros(max(cap, 1), dtype=CAND_DTYPE)
+        return self._out[:cap]
+
     def search(self, t, tsamp: float, zmax: float = None, dz: float = None, numharm: int = None,
                sigma: float = 6.0, cap: int = 1 << 16, stream=None, allow_trunc: bool = False):
         """Candidates (structured numpy array, CAND_DTYPE) sorted by (series, harm, r_idx).
@@ -216,7 +227,7 @@ class Plan:
         zmax = self.zmax if zmax is None else zmax
         dz = self.dz if dz is None else dz
         numharm = self.numharm if numharm is None else numharm
-        out = np.zeros(int(cap), dtype=CAND_DTYPE)
+        out = self._staging(cap)
         n = ctypes.c_int64(0)
         st = self.lib.fdas_search(self.handle, ctypes.c_void_p(t.data_ptr()), t.shape[1], t.shape[0],
                                   float(tsamp), float(zmax), float(dz), int(numharm), float(sigma),
@@ -249,7 +260,7 @@ class Plan:
             raise ValueError("a series lies outside the buffer")
         dz = self.dz if dz is None else dz
         numharm = self.numharm if numharm is None else numharm
-        out = np.zeros(int(cap), dtype=CAND_DTYPE)
+        out = self._staging(cap)
         n = ctypes.c_int64(0)
         i64 = ctypes.POINTER(ctypes.c_int64)
         f64 = ctypes.POINTER(ctypes.c_double)
@@ -334,7 +345,7 @@ class Plan:
         zmax = self.zmax if zmax is None else zmax
         dz = self.dz if dz is None else dz
         numharm = self.numharm if numharm is None else numharm
-        out = np.zeros(int(cap), dtype=CAND_DTYPE)
+        out = self._staging(cap)
         n = ctypes.c_int64(0)
         st = self.lib.fdas_harmsum(self.handle, ctypes.c_void_p(plane.data_ptr()), int(nsamp),
                                    plane.shape[0], float(tsamp), float(zmax), float(dz), int(numharm),

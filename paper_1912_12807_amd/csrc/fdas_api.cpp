@@ -723,7 +723,7 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
             c.fdot_hz_s = c.z_fund / (T * T);
         }
     };
-    const int64_t per_thread = 2048;
+    const int64_t per_thread = 16384;   // records per host thread (spawning costs tens of us)
     const int nth = (int)std::min<int64_t>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
                                            (n + per_thread - 1) / per_thread);
     if (nth <= 1) {
