@@ -33,11 +33,11 @@ template <int L>
 struct Corr {
     static constexpr int T = L / 8;          // threads per workgroup
     static constexpr int R4 = L / 512;       // radix of the fourth pass (1: none)
-    static constexpr int LDSZ = L + L / 8;   // floats per array (largest padded layout)
+    static constexpr int LDSZ = L + L / 8;   // complex slots per buffer (largest padded layout)
     // read strides between a thread's points t + q T in the three exchange layouts
-    static constexpr int RS1 = T + T / 64;   // layout 1: word p at p + p/64
-    static constexpr int RS2 = T + T / 8;    // layout 2: word p at p + 8 (p/64)
-    static constexpr int RS3 = T;            // layout 3: word p at p
+    static constexpr int RS1 = T + T / 32;   // layout 1: point p at p + p/32
+    static constexpr int RS2 = T + T / 8;    // layout 2: point p at p + 8 (p/64)
+    static constexpr int RS3 = T;            // layout 3: point p at p
 };
 
 template <int L>
@@ -113,23 +113,21 @@ __device__ __forceinline__ void pass4_butterfly(float2 *v, const Twiddles<L> &tw
 // write v[r] at wbase + r*WS of buffer sel, barrier, read the thread's points
 // back from rbase + q*RS.
 //
-// Each exchange has its own layout, chosen so that a wave's 64 lanes hit 64
-// distinct LDS banks both when writing the pass outputs (position 8t + r after
-// pass 1, 64(t/8) + t%8 + 8r after pass 2, 512(t/64) + t%64 + 64r after pass
-// 3) and when reading t + qT back: word p is stored at p + p/64 (exchange 1),
-// p + 8(p/64) (exchange 2) and p (exchange 3).
+// Points are exchanged as 8-byte complex values (one LDS instruction each).
+// Each exchange has its own layout, chosen so that each half wave's 32 lanes
+// (an 8-byte access covers two 4-byte banks) hit 32 distinct bank pairs both
+// when writing the pass outputs (position 8t + r after pass 1, 64(t/8) + t%8
+// + 8r after pass 2, 512(t/64) + t%64 + 64r after pass 3) and when reading
+// t + qT back: point p is stored at p + p/32 (exchange 1), p + 8(p/64)
+// (exchange 2) and p (exchange 3).
 template <int L, int WS, int RS>
 __device__ __forceinline__ void exchange(float2 *v, float *lds, int &sel, int wbase, int rbase) {
-    float *re = lds + sel * 2 * Corr<L>::LDSZ;
-    float *im = re + Corr<L>::LDSZ;
+    float2 *cx = reinterpret_cast<float2 *>(lds) + sel * Corr<L>::LDSZ;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        re[wbase + r * WS] = v[r].x;
-        im[wbase + r * WS] = v[r].y;
-    }
+    for (int r = 0; r < 8; ++r) cx[wbase + r * WS] = v[r];
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = make_float2(re[rbase + q * RS], im[rbase + q * RS]);
+    for (int q = 0; q < 8; ++q) v[q] = cx[rbase + q * RS];
     sel ^= 1;
 }
 
@@ -179,7 +177,7 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
                                            const int32_t *__restrict__ blk_lo,
                                            const int32_t *__restrict__ blk_of_row) {
     constexpr int T = Corr<L>::T;
-    __shared__ float lds[4 * Corr<L>::LDSZ];
+    __shared__ __align__(16) float lds[4 * Corr<L>::LDSZ];
     const int t = threadIdx.x;
 
     // XCD-aware decomposition: xcd = id mod 8 serves z group (xcd mod G)
@@ -198,10 +196,10 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
     Twiddles<L> tw;
     make_twiddles<L>(tw, t);
     LdsAddr a;
-    a.w1 = 8 * t + (t >> 3);                 // pass-1 output 8t + r in layout 1
+    a.w1 = 8 * t + (t >> 2);                 // pass-1 output 8t + r in layout 1
     a.w2 = 72 * (t >> 3) + (t & 7);          // pass-2 output 64(t/8) + t%8 + 8r in layout 2
     a.w3 = 512 * (t >> 6) + (t & 63);        // pass-3 output 512(t/64) + t%64 + 64r in layout 3
-    a.r1 = t + (t >> 6);
+    a.r1 = t + (t >> 5);
     a.r2 = t + 8 * (t >> 6);
     a.r3 = t;
     int sel = 0;
