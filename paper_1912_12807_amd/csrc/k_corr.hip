@@ -13,9 +13,9 @@
 //
 // FFT layout: L points over T = L/8 threads, thread t holding points t + q T
 // (q = 0..7) in natural order before every pass. Stockham radix-8 passes with
-// Ns = 1, 8, 64, then a radix-(L/512) pass, exchange through LDS (separate
-// re/im arrays, a bank-conflict-free layout per exchange, ping-pong buffers,
-// one barrier per exchange); after the last pass each thread again holds
+// Ns = 1, 8, 64, then a radix-(L/512) pass, exchange through LDS (8-byte
+// complex values, a bank-conflict-free layout per exchange, ping-pong
+// buffers, one barrier per exchange); after the last pass each thread again holds
 // t + q T, so plane rows are written with coalesced stores.
 //
 // Work is split so that each XCD (workgroup id mod 8) only touches one group
