@@ -178,7 +178,6 @@ class Plan:
     """A device plan: template bank and workspace for series up to max_nsamp."""
 
     def __init__(self, max_nsamp: int, max_series: int, zmax: float, dz: float, numharm: int, **opts):
-        self._out = None
         self.lib = load()
         self.opts = default_opts(**opts)
         self.handle = ctypes.c_void_p()
@@ -208,15 +207,17 @@ class Plan:
         return geometry(nsamp, tsamp, self.zmax if zmax is None else zmax,
                         self.dz if dz is None else dz, self.opts)
 
-    def _staging(self, cap: int):
-        """Reused host buffer for the library's records (the caller gets copies):
-        a fresh buffer per call would page-fault its written part every time."""
+    @staticmethod
+    def _records(cap: int):
+        """Fresh, uninitialised host array for up to cap records. The library's
+        host threads write the records straight into it and the caller gets a
+        view of the written prefix: no copy, and pages past it are never
+        touched (a long list costs its page faults once, spread over those
+        threads, instead of a fault-and-copy pass on one)."""
         cap = int(cap)
         if cap < 0:
             raise ValueError("cap must be >= 0")
-        if self._out is None or len(self._out) < cap:
-            self._out = np.zeros(max(cap, 1), dtype=CAND_DTYPE)
-        return self._out[:cap]
+        return np.empty(max(cap, 1), dtype=CAND_DTYPE)[:cap]
 
     def search(self, t, tsamp: float, zmax: float = None, dz: float = None, numharm: int = None,
                sigma: float = 6.0, cap: int = 1 << 16, stream=None, allow_trunc: bool = False):
@@ -227,17 +228,17 @@ class Plan:
         zmax = self.zmax if zmax is None else zmax
         dz = self.dz if dz is None else dz
         numharm = self.numharm if numharm is None else numharm
-        out = self._staging(cap)
+        out = self._records(cap)
         n = ctypes.c_int64(0)
         st = self.lib.fdas_search(self.handle, ctypes.c_void_p(t.data_ptr()), t.shape[1], t.shape[0],
                                   float(tsamp), float(zmax), float(dz), int(numharm), float(sigma),
                                   out.ctypes.data_as(ctypes.c_void_p), int(cap), ctypes.byref(n),
                                   _stream_handle(stream))
         if allow_trunc and st in (FDAS_OK, FDAS_E_TRUNC):
-            return out[:min(int(cap), int(n.value))].copy(), int(n.value)
+            return out[:min(int(cap), int(n.value))], int(n.value)
         if st != FDAS_OK:
             self._raise(st, "fdas_search")
-        return out[:n.value].copy()
+        return out[:n.value]
 
     def search_ragged(self, buf, offsets, nsamp, tsamp, zmax, dz: float = None, numharm: int = None,
                       sigma: float = 6.0, cap: int = 1 << 16, stream=None, allow_trunc: bool = False):
@@ -260,7 +261,7 @@ class Plan:
             raise ValueError("a series lies outside the buffer")
         dz = self.dz if dz is None else dz
         numharm = self.numharm if numharm is None else numharm
-        out = self._staging(cap)
+        out = self._records(cap)
         n = ctypes.c_int64(0)
         i64 = ctypes.POINTER(ctypes.c_int64)
         f64 = ctypes.POINTER(ctypes.c_double)
@@ -271,10 +272,10 @@ class Plan:
                                          out.ctypes.data_as(ctypes.c_void_p), int(cap), ctypes.byref(n),
                                          _stream_handle(stream))
         if allow_trunc and st in (FDAS_OK, FDAS_E_TRUNC):
-            return out[:min(int(cap), int(n.value))].copy(), int(n.value)
+            return out[:min(int(cap), int(n.value))], int(n.value)
         if st != FDAS_OK:
             self._raise(st, "fdas_search_ragged")
-        return out[:n.value].copy()
+        return out[:n.value]
 
     def tuning(self) -> str:
         """The autotuner's choices as text (one line per shape)."""
@@ -345,7 +346,7 @@ class Plan:
         zmax = self.zmax if zmax is None else zmax
         dz = self.dz if dz is None else dz
         numharm = self.numharm if numharm is None else numharm
-        out = self._staging(cap)
+        out = self._records(cap)
         n = ctypes.c_int64(0)
         st = self.lib.fdas_harmsum(self.handle, ctypes.c_void_p(plane.data_ptr()), int(nsamp),
                                    plane.shape[0], float(tsamp), float(zmax), float(dz), int(numharm),
@@ -353,7 +354,7 @@ class Plan:
                                    ctypes.byref(n), _stream_handle(stream))
         if st != FDAS_OK:
             self._raise(st, "fdas_harmsum")
-        return out[:n.value].copy()
+        return out[:n.value]
 
     def plane(self, t, tsamp: float, zmax: float = None, dz: float = None, stream=None):
         """Normalised power plane, CUDA float32 [B][NZ][NR] (column c is R = c + 2 rlo)."""

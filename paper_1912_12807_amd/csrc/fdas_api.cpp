@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <list>
 #include <map>
 #include <sstream>
@@ -678,35 +679,68 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
         HIPTRY(p, hipStreamSynchronize(st));
     }
     p->collect();
-    for (int64_t i = 0; i < n; ++i) {
-        const DevCand &d = p->h_rec[i];
-        if (d.b < 0 || d.b >= (int)B.vmap.size() || d.s < 0 || d.s > 5)
-            return p->fail(FDAS_E_DEVICE, "internal error: candidate of an unknown series or stage");
-        const Geometry &g = B.groups[B.vgroup[d.b]].g;
-        if (d.zq < -g.Z || d.zq > g.Z)
-            return p->fail(FDAS_E_DEVICE, "internal error: candidate without a maximising drift");
-    }
-    // Device records are in (batch slot, stage, column) order, and each slot
-    // holds one caller series: a stable counting sort by caller series gives
-    // the (series, harm, r_idx) order. Only the first cap ranks are written.
-    std::vector<int64_t> rank;
-    if (!sorted_on_device) {
-        int ns = 0;
-        for (int v : B.vmap) ns = std::max(ns, v + 1);
-        std::vector<int64_t> next((size_t)ns + 1, 0);
-        for (int64_t i = 0; i < n; ++i) ++next[(size_t)B.vmap[p->h_rec[i].b] + 1];
-        for (int k = 0; k < ns; ++k) next[k + 1] += next[k];
-        rank.resize((size_t)n);
-        for (int64_t i = 0; i < n; ++i) rank[i] = next[B.vmap[p->h_rec[i].b]]++;
-    }
+    // Two passes over host threads (long lists reach millions of records).
+    // Device records are in (batch slot, stage, column) order and each slot
+    // holds one caller series, so a stable counting sort by caller series
+    // gives the (series, harm, r_idx) order: pass 1 checks the records and
+    // counts each thread's records per series, the ranks follow series-major
+    // then thread-major, and pass 2 writes each record (with units; the FP64
+    // significance comes from the device) at its rank. Only ranks below cap
+    // are written.
     const int64_t lim = std::min(n, cap);
-    // units (the FP64 significance comes from the device), over host threads
-    // for long lists
-    auto convert = [&](int64_t i0, int64_t i1) {
+    const int64_t per_thread = 16384;   // records per host thread (spawning costs tens of us)
+    const int nth = (int)std::max<int64_t>(
+        1, std::min<int64_t>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
+                             (n + per_thread - 1) / per_thread));
+    auto over_threads = [&](const std::function<void(int, int64_t, int64_t)> &fn) {
+        if (nth == 1) {
+            fn(0, 0, n);
+            return;
+        }
+        std::vector<std::thread> pool;
+        for (int w = 0; w < nth; ++w) pool.emplace_back(fn, w, n * w / nth, n * (w + 1) / nth);
+        for (auto &t : pool) t.join();
+    };
+    int ns = 0;
+    for (int v : B.vmap) ns = std::max(ns, v + 1);
+    const size_t row = (size_t)ns + 8;   // per-thread counters, a cache line apart
+    std::vector<int64_t> next(sorted_on_device ? 0 : (size_t)nth * row, 0);
+    std::vector<char> bad((size_t)nth, 0);
+    over_threads([&](int w, int64_t i0, int64_t i1) {
         for (int64_t i = i0; i < i1; ++i) {
-            const int64_t k = rank.empty() ? i : rank[i];
-            if (k >= lim) continue;
             const DevCand &d = p->h_rec[i];
+            if (d.b < 0 || d.b >= (int)B.vmap.size() || d.s < 0 || d.s > 5) {
+                bad[w] = 1;
+                return;
+            }
+            const Geometry &g = B.groups[B.vgroup[d.b]].g;
+            if (d.zq < -g.Z || d.zq > g.Z) {
+                bad[w] = 2;
+                return;
+            }
+            if (!sorted_on_device) ++next[(size_t)w * row + B.vmap[d.b]];
+        }
+    });
+    for (int w = 0; w < nth; ++w) {
+        if (bad[w] == 1) return p->fail(FDAS_E_DEVICE, "internal error: candidate of an unknown series or stage");
+        if (bad[w] == 2) return p->fail(FDAS_E_DEVICE, "internal error: candidate without a maximising drift");
+    }
+    if (!sorted_on_device) {
+        int64_t acc = 0;
+        for (int v = 0; v < ns; ++v)
+            for (int w = 0; w < nth; ++w) {
+                int64_t &c = next[(size_t)w * row + v];
+                const int64_t k = c;
+                c = acc;
+                acc += k;
+            }
+    }
+    over_threads([&](int w, int64_t i0, int64_t i1) {
+        int64_t *nx = sorted_on_device ? nullptr : next.data() + (size_t)w * row;
+        for (int64_t i = i0; i < i1; ++i) {
+            const DevCand &d = p->h_rec[i];
+            const int64_t k = nx ? nx[B.vmap[d.b]]++ : i;
+            if (k >= lim) continue;
             const Geometry &g = B.groups[B.vgroup[d.b]].g;
             const int H = 1 << d.s;
             const double T = B.vT[d.b];
@@ -722,17 +756,7 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
             c.f_hz = c.r_fund / T;
             c.fdot_hz_s = c.z_fund / (T * T);
         }
-    };
-    const int64_t per_thread = 16384;   // records per host thread (spawning costs tens of us)
-    const int nth = (int)std::min<int64_t>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
-                                           (n + per_thread - 1) / per_thread);
-    if (nth <= 1) {
-        convert(0, n);
-    } else {
-        std::vector<std::thread> pool;
-        for (int w = 0; w < nth; ++w) pool.emplace_back(convert, n * w / nth, n * (w + 1) / nth);
-        for (auto &t : pool) t.join();
-    }
+    });
     *n_total = total;
     return total > cap ? FDAS_E_TRUNC : FDAS_OK;
 }
