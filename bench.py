@@ -302,8 +302,8 @@ def main():
     x = torch.from_numpy(synth.generate(wl)).cuda()
     rlo, nr, nz = fdas.geometry(wl.nsamp, wl.tsamp, wl.zmax, wl.dz)
     cells = wl.nseries * nr * nz
-    plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1, autotune=args.autotune,
-                     seg_len=args.seg_len, harm_block=args.harm_block, harm_pair=args.harm_pair)
+    popts = dict(seg_len=args.seg_len, harm_block=args.harm_block, harm_pair=args.harm_pair)
+    plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, autotune=args.autotune, **popts)
     if args.tuning:
         plan.load_tuning(args.tuning.replace(";", "\n"))
     if args.copy_calibration:
@@ -321,7 +321,6 @@ def main():
     for _ in range(args.warmup):
         cands, ncand = plan.search(x, wl.tsamp, sigma=wl.sigma, cap=cap, allow_trunc=True)
     torch.cuda.synchronize()
-    plan.profile(reset=True)
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -329,13 +328,30 @@ def main():
         cands, ncand = plan.search(x, wl.tsamp, sigma=wl.sigma, cap=cap, allow_trunc=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = plan.profile(reset=True)
     tuning = plan.tuning().strip()
+    info = plan.info()
+    plan.close()
     ms_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall
 
+    # per-phase kernel times (HIP events on the search stream) from a plan with
+    # the same launch parameters and profiling on, which runs every phase in
+    # order on the one stream
+    print(f"[bench] phase timing {args.steps} steps", file=sys.stderr, flush=True)
+    pplan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1, **popts)
+    if tuning:
+        pplan.load_tuning(tuning)
+    pc, _ = pplan.search(x, wl.tsamp, sigma=wl.sigma, cap=cap, allow_trunc=True)
+    torch.cuda.synchronize()
+    pplan.profile(reset=True)
+    for _ in range(args.steps):
+        pplan.search(x, wl.tsamp, sigma=wl.sigma, cap=cap, allow_trunc=True)
+    torch.cuda.synchronize()
+    prof = pplan.profile(reset=True)
+    pplan.close()
+    assert np.array_equal(pc, cands), "the profiled plan found other candidates"
+
     # dominant kernel and its roofline
-    info = plan.info()
     phases = {k: v[0] / args.steps for k, v in prof.items()}
     dom = max(("plane", "harmsum"), key=lambda k: prof[k][0])
     launches = max(1, prof[dom][1])
