@@ -73,7 +73,11 @@ int zgroups_of(int NZ) {
     while (G < 8 && NZ >= 2 * G * 12) G *= 2;
     return G;
 }
-int default_block_rows(int numharm) { return numharm <= 8 ? 10 : numharm == 16 ? 8 : 6; }
+// Drift rows per bound block. Above 8 harmonics, longer blocks are more often
+// hot (a strong line enters many stage sums) and cost more when they are:
+// 32 x 2^23 series with mains tones at numharm 16 took 83, 66, 68 and 99 ms of
+// harmonic sums with 4, 6, 8 and 10 rows.
+int default_block_rows(int numharm) { return numharm <= 8 ? 10 : 6; }
 // Block maxima per bin (both half-bin columns) or per column. Per column bounds
 // are tighter at twice the memory; above 8 harmonics, where a strong line's
 // half-bin neighbours enter many more stage sums, they win (e.g. 347 -> 227 ms

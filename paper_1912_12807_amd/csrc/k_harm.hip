@@ -524,34 +524,58 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ maxv,
 }
 
 // Exclusive scan of the block counts, offset by the running total in state[0].
+// The 1024 threads sweep the counts in tiles of 4096, four consecutive counts
+// per thread (one coalesced 16-byte load), each tile scanned by wave shuffles
+// and then across the 16 wave totals.
 __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict__ counts,
                                                       int64_t nblk, int64_t *__restrict__ offsets,
                                                       int64_t *__restrict__ state) {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (nblk + 1023) / 1024;
-    const int64_t lo = t * per;
-    const int64_t hi = lo + per < nblk ? lo + per : nblk;
-    int64_t sum = 0;
-    for (int64_t i = lo; i < hi; ++i) sum += counts[i];
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t x = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
-    }
+    __shared__ int64_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int64_t base0 = state[0];
-    int64_t run = base0 + part[t] - sum;
-    for (int64_t i = lo; i < hi; ++i) {
-        offsets[i] = run;
-        run += counts[i];
+    int64_t carry = base0;
+    for (int64_t i0 = 0; i0 < nblk; i0 += 4096) {
+        const int64_t i = i0 + 4 * (int64_t)t;
+        int c[4];
+        if (i + 3 < nblk) {
+            const int4 v = *reinterpret_cast<const int4 *>(counts + i);
+            c[0] = v.x;
+            c[1] = v.y;
+            c[2] = v.z;
+            c[3] = v.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = i + q < nblk ? counts[i + q] : 0;
+        }
+        const int64_t sum = (int64_t)c[0] + c[1] + c[2] + c[3];
+        int64_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[wid] = incl;
+        __syncthreads();
+        int64_t wbase = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const int64_t x = wsum[w];
+            if (w < wid) wbase += x;
+            tot += x;
+        }
+        __syncthreads();   // wsum is rewritten by the next tile
+        int64_t run = carry + wbase + incl - sum;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (i + q < nblk) offsets[i + q] = run;
+            run += c[q];
+        }
+        carry += tot;
     }
-    __syncthreads();
+    __syncthreads();   // every thread has read state[0]
     if (t == 0) {
         state[1] = base0;
-        state[0] = base0 + part[1023];
+        state[0] = carry;
     }
 }
 
