@@ -545,9 +545,6 @@ fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
         HIPTRY(p, launch_compact(p->d_maxv, p->d_zarg, (int64_t)n * NS * mpitch, mpitch, NS, vbase + b0, p->d_thr,
                                  p->d_counts, p->d_offsets, p->d_state, p->d_rec, p->rec_cap, st));
         p->end(4, e, st);
-        e = p->begin(st);
-        HIPTRY(p, launch_cand_sigma(p->d_rec, p->d_state, p->rec_cap, st));
-        p->end(5, e, st);
     }
     return FDAS_OK;
 }
@@ -783,6 +780,10 @@ fdas_status enqueue_groups(fdas_plan p, const float *x, bool ragged, const Batch
             TRY(run_chunks(p, G.g, *bk, G.cfg, numharm, G.nb, G.vbase, false, st));
         }
     }
+    // significance of every record of the call, in one launch
+    hipEvent_t e = p->begin(st);
+    HIPTRY(p, launch_cand_sigma(p->d_rec, p->d_state, p->rec_cap, st));
+    p->end(5, e, st);
     return FDAS_OK;
 }
 
@@ -1459,10 +1460,10 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
             HIPTRY(p, launch_compact(p->d_maxv, p->d_zarg, (int64_t)nb * NS * mpitch, mpitch, NS, b0, p->d_thr,
                                      p->d_counts, p->d_offsets, p->d_state, p->d_rec, p->rec_cap, st));
             p->end(4, e, st);
-            e = p->begin(st);
-            HIPTRY(p, launch_cand_sigma(p->d_rec, p->d_state, p->rec_cap, st));
-            p->end(5, e, st);
         }
+        hipEvent_t e = p->begin(st);
+        HIPTRY(p, launch_cand_sigma(p->d_rec, p->d_state, p->rec_cap, st));
+        p->end(5, e, st);
         bool regrow = false;
         const fdas_status s = finish(p, B, dz, true, out_host, cap, n_total, st, &regrow);
         if (!regrow) return s;

@@ -158,7 +158,7 @@ hipError_t launch_compact(const float *maxv, const int16_t *zarg, int64_t nelem,
                           int nstages, int b0, const float *thr_dev, int32_t *counts, int64_t *offsets,
                           int64_t *state, DevCand *out, int64_t cap, hipStream_t st);
 
-// FP64 significance of this chunk's records [state[1], min(state[0], cap))
+// FP64 significance of the records [0, min(state[0], cap)) of the call
 // (the host statistics' arithmetic).
 hipError_t launch_cand_sigma(DevCand *rec, const int64_t *state, int64_t cap, hipStream_t st);
 

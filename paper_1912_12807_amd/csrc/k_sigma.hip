@@ -76,12 +76,12 @@ __device__ static double dev_sigma(int H, double power) {
     return s;
 }
 
-// records [state[1], min(state[0], cap)): the current chunk's candidates
+// records [0, min(state[0], cap)): every record of the call, launched once
+// after its last compaction
 __global__ __launch_bounds__(256) void k_cand_sigma(DevCand *__restrict__ rec, const int64_t *__restrict__ state,
                                                     int64_t cap) {
-    const int64_t begin = state[1];
     const int64_t end = state[0] < cap ? state[0] : cap;
-    for (int64_t i = begin + (int64_t)blockIdx.x * 256 + threadIdx.x; i < end; i += (int64_t)gridDim.x * 256)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < end; i += (int64_t)gridDim.x * 256)
         rec[i].sigma = dev_sigma(1 << rec[i].s, (double)rec[i].power);
 }
 
