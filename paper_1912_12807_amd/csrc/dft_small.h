@@ -1,4 +1,4 @@
-// Register-resident complex helpers and small DFTs (radix 2, 4, 8) for the
+// Register-resident complex helpers and small DFTs (radix 2 to 32) for the
 // FFT kernels. DIR = -1 computes X_k = sum_n v_n exp(-2 pi i n k / R),
 // DIR = +1 the unnormalised inverse. Complex values are float2 (x = re, y = im).
 #pragma once
@@ -87,14 +87,83 @@ __device__ __forceinline__ void dft8(float2 *v) {
     v[7] = csub(e3, w3);
 }
 
+// a * exp(DIR 2 pi i K / 32) for a compile-time K in [0, 16)
+template <int K, int DIR>
+__device__ __forceinline__ float2 rot32(float2 a) {
+    if constexpr (K == 0) {
+        return a;
+    } else if constexpr (K == 8) {
+        return cmul_i<DIR>(a);
+    } else {
+        // cos(m pi / 16), m = 0..8
+        constexpr float T[9] = {1.0f,
+                                0.980785280403230449126f,
+                                0.923879532511286756128f,
+                                0.831469612302545237079f,
+                                0.707106781186547524401f,
+                                0.555570233019602224743f,
+                                0.382683432365089771728f,
+                                0.195090322016128267848f,
+                                0.0f};
+        constexpr float c = K <= 8 ? T[K] : -T[16 - K];
+        constexpr float s = K <= 8 ? T[8 - K] : T[K - 8];
+        return cmul(a, make_float2(c, DIR * s));
+    }
+}
+
+// radix-2 combination of the half-length DFTs e (even inputs) and o (odd):
+// v[k] = e[k] + w^k o[k], v[k + H] = e[k] - w^k o[k], w = exp(DIR 2 pi i / (2 H))
+template <int H, int DIR, int K = 0>
+__device__ __forceinline__ void combine2(float2 *v, const float2 *e, const float2 *o) {
+    if constexpr (K < H) {
+        const float2 t = rot32<K * (16 / H), DIR>(o[K]);
+        v[K] = cadd(e[K], t);
+        v[K + H] = csub(e[K], t);
+        combine2<H, DIR, K + 1>(v, e, o);
+    }
+}
+
+// in-place 16- and 32-point DFTs (natural order in and out): even/odd split
+// into two half-length DFTs and one radix-2 combination
+template <int DIR>
+__device__ __forceinline__ void dft16(float2 *v) {
+    float2 e[8], o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        e[i] = v[2 * i];
+        o[i] = v[2 * i + 1];
+    }
+    dft8<DIR>(e);
+    dft8<DIR>(o);
+    combine2<8, DIR>(v, e, o);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft32(float2 *v) {
+    float2 e[16], o[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        e[i] = v[2 * i];
+        o[i] = v[2 * i + 1];
+    }
+    dft16<DIR>(e);
+    dft16<DIR>(o);
+    combine2<16, DIR>(v, e, o);
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft_r(float2 *v) {
     if constexpr (R == 2) {
         dft2<DIR>(v[0], v[1]);
     } else if constexpr (R == 4) {
         dft4<DIR>(v[0], v[1], v[2], v[3]);
-    } else {
+    } else if constexpr (R == 8) {
         dft8<DIR>(v);
+    } else if constexpr (R == 16) {
+        dft16<DIR>(v);
+    } else {
+        static_assert(R == 32, "radix 2, 4, 8, 16 or 32");
+        dft32<DIR>(v);
     }
 }
 

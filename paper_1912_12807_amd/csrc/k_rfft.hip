@@ -4,11 +4,13 @@
 // series (the "FFT of the dedispersed series" step of the pipeline, paper
 // Section 2, step 3). The N real samples are read as N/2 complex values
 // z_n = x_2n + i x_2n+1, transformed by a batched Stockham autosort FFT of
-// length M = N/2 (one launch per radix-8/4/2 pass, every pass reading and
-// writing coalesced rows), and split into the real spectrum by
+// length M = N/2 (one launch per radix-32 pass after one of radix 2 to 16,
+// every pass reading and writing coalesced rows), and split into the real
+// spectrum by
 //   A_k = E_k + exp(-2 pi i k / N) O_k,  E_k = (Z_k + conj Z_{M-k}) / 2,
 //   O_k = (Z_k - conj Z_{M-k}) / (2 i),  Z_M = Z_0.
-// Twiddles come from sincospi of exactly representable arguments 2 j / n.
+// Twiddles come from sincospi of exactly representable arguments 2 j / n
+// (powers of two of a pass's base twiddle; the others are products of them).
 #include "dft_small.h"
 #include "fdas_internal.h"
 
@@ -32,9 +34,23 @@ __global__ __launch_bounds__(256) void k_stockham_pass(const float2 *__restrict_
     for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
     const int64_t k = j & (Ns - 1);
     if (Ns > 1) {
-        const float inv = 2.0f / (float)(Ns * R);
+        // twiddle w^r, w = exp(DIR 2 pi i k / (Ns R)): the powers w^(2^b) from
+        // sincospi of exactly representable arguments, every other power as
+        // w^(r - 2^b) w^(2^b) for the lowest set bit b of r (at most log2 R
+        // rounded products deep)
+        const float base = (float)DIR * (float)k * (2.0f / (float)(Ns * R));
+        float2 w[R];
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], expipi((float)DIR * (float)(k * r) * inv));
+        for (int r = 1; r < R; ++r) {
+            if ((r & (r - 1)) == 0) {
+                w[r] = expipi(base * (float)r);
+            } else {
+                const int low = r & -r;
+                w[r] = cmul(w[r - low], w[low]);
+            }
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
     }
     dft_r<R, DIR>(v);
     const int64_t o = (j - k) * R + k;
@@ -69,26 +85,32 @@ hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float
     if (M < 4 || (M & (M - 1)) || nseries < 1 || nseries > 65535) return hipErrorInvalidValue;
     int p = 0;
     while ((int64_t(1) << p) < M) ++p;
-    // radix sequence: a leading 2 or 4 absorbs p mod 3, then radix 8
+    // radix sequence: a leading 2, 4, 8 or 16 absorbs p mod 5, then radix 32
+    // (each pass is one read and one write of the batch: 2^17 points take 4
+    // passes, 2^22 take 5)
     const float2 *src = reinterpret_cast<const float2 *>(x);
     int64_t pin = M;
     float2 *bufs[2] = {w0, w1};
     int which = 0;
     int64_t Ns = 1;
-    int rem = p % 3;
+    const int rem = p % 5;
     if (rem) {
-        if (rem == 1) pass<2>(src, bufs[which], M, Ns, pin, M, nseries, offs, st);
-        else pass<4>(src, bufs[which], M, Ns, pin, M, nseries, offs, st);
+        switch (rem) {
+        case 1: pass<2>(src, bufs[which], M, Ns, pin, M, nseries, offs, st); break;
+        case 2: pass<4>(src, bufs[which], M, Ns, pin, M, nseries, offs, st); break;
+        case 3: pass<8>(src, bufs[which], M, Ns, pin, M, nseries, offs, st); break;
+        default: pass<16>(src, bufs[which], M, Ns, pin, M, nseries, offs, st); break;
+        }
         offs = nullptr;
-        Ns *= (rem == 1) ? 2 : 4;
+        Ns <<= rem;
         src = bufs[which];
         which ^= 1;
         pin = M;
     }
     while (Ns < M) {
-        pass<8>(src, bufs[which], M, Ns, pin, M, nseries, offs, st);
+        pass<32>(src, bufs[which], M, Ns, pin, M, nseries, offs, st);
         offs = nullptr;
-        Ns *= 8;
+        Ns *= 32;
         src = bufs[which];
         which ^= 1;
         pin = M;
