@@ -25,7 +25,9 @@
  *
  * Conventions: every pointer argument named *_dev is device memory of the
  * current HIP device, *_host is host memory. Calls return an fdas_status and
- * never abort or throw across the ABI. A plan is not thread safe: use one
+ * never abort or throw across the ABI (a failed host allocation inside a call
+ * returns FDAS_E_NOMEM, with the message in fdas_last_error when a plan is
+ * given). A plan is not thread safe: use one
  * plan per host thread / stream. Calls that take a stream enqueue their work
  * on it (NULL = the default stream) and return only after the work is done.
  */

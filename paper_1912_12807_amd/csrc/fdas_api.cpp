@@ -14,6 +14,7 @@
 #include "fdas_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -68,6 +69,28 @@ int nstages_of(int numharm) {
     return s + 1;
 }
 bool valid_numharm(int h) { return h == 1 || h == 2 || h == 4 || h == 8 || h == 16 || h == 32; }
+bool run_parallel(int n, const std::function<void(int)> &fn) {
+    std::atomic<bool> ok{true};
+    auto share = [&](int w) {
+        try {
+            fn(w);
+        } catch (...) {
+            ok = false;
+        }
+    };
+    std::vector<std::thread> pool;
+    int w = 1;
+    try {
+        pool.reserve(n > 1 ? (size_t)n - 1 : 0);
+        for (; w < n; ++w) pool.emplace_back(share, w);
+    } catch (...) {
+    }
+    for (int v = w; v < n; ++v) share(v);
+    if (n > 0) share(0);
+    for (auto &t : pool) t.join();
+    return ok;
+}
+
 int zgroups_of(int NZ) {
     int G = 1;
     while (G < 8 && NZ >= 2 * G * 12) G *= 2;
@@ -344,17 +367,14 @@ fdas_status get_bank(fdas_plan p, double zmax, double dz, int L, const Bank **ou
     const int mseg = half_width(Z * dz, K);
     if (!seg_len_ok(L, mseg)) return p->fail(FDAS_E_UNSUPPORTED, "segment length too short for zmax");
     std::vector<float> host((size_t)NZ * 2 * L * 2);
-    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    for (unsigned w = 0; w < nth; ++w) {
-        pool.emplace_back([&, w]() {
-            for (int row = (int)w; row < 2 * NZ; row += (int)nth) {
-                const int zi = row / 2, par = row % 2;
-                kernel_spectrum((zi - Z) * dz, par, K, L, mseg, host.data() + (size_t)row * L * 2);
-            }
-        });
-    }
-    for (auto &t : pool) t.join();
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const bool built = run_parallel(nth, [&](int w) {
+        for (int row = w; row < 2 * NZ; row += nth) {
+            const int zi = row / 2, par = row % 2;
+            kernel_spectrum((zi - Z) * dz, par, K, L, mseg, host.data() + (size_t)row * L * 2);
+        }
+    });
+    if (!built) return p->fail(FDAS_E_NOMEM, "template bank: host computation failed");
     evict<Bank>(p, p->banks, kMaxBanks, [](Bank &b) -> void * { return b.d; });
     Bank b;
     b.zmax = zmax;
@@ -694,13 +714,7 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
         1, std::min<int64_t>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
                              (n + per_thread - 1) / per_thread));
     auto over_threads = [&](const std::function<void(int, int64_t, int64_t)> &fn) {
-        if (nth == 1) {
-            fn(0, 0, n);
-            return;
-        }
-        std::vector<std::thread> pool;
-        for (int w = 0; w < nth; ++w) pool.emplace_back(fn, w, n * w / nth, n * (w + 1) / nth);
-        for (auto &t : pool) t.join();
+        (void)run_parallel(nth, [&](int w) { fn(w, n * w / nth, n * (w + 1) / nth); });
     };
     int ns = 0;
     for (int v : B.vmap) ns = std::max(ns, v + 1);
@@ -893,6 +907,9 @@ void key_group(std::ostringstream &k, const Group &G) {
 
 }  // namespace
 
+// entry-point error handler: records the message on the plan (if any)
+static fdas_status plan_entry_error(fdas_plan p, fdas_status s, const char *msg) { return p ? p->fail(s, msg) : s; }
+
 extern "C" {
 
 void fdas_plan_opts_default(fdas_plan_opts *o) {
@@ -963,6 +980,7 @@ void fdas_plan_destroy(fdas_plan p) {
 
 fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_series, double zmax,
                              double dz, int32_t numharm, const fdas_plan_opts *opts) {
+    FDAS_ENTRY_TRY
     if (!out) return FDAS_E_INVAL;
     *out = nullptr;
     fdas_plan_opts o;
@@ -1051,11 +1069,13 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     if ((s = halloc(p, &p->h_rec, p->h_rec_cap, "candidate staging")) != FDAS_OK) return bail(s);
     *out = p;
     return FDAS_OK;
+    FDAS_ENTRY_CATCH(plan_entry_error, nullptr)
 }
 
 fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
                         double tsamp, double zmax, double dz, int32_t numharm, double sigma,
                         fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream) {
+    FDAS_ENTRY_TRY
     Geometry g;
     TRY(check_common(p, series_dev, nsamp, nseries, tsamp, zmax, dz, g));
     TRY(check_search(p, numharm, sigma, out_host, cap, n_total));
@@ -1078,12 +1098,14 @@ fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int
     key << "h " << (const void *)series_dev << ' ' << dz << ' ' << numharm << ' ' << p->rec_cap;
     key_group(key, G);
     return run_batch(p, series_dev, false, B, dz, numharm, key.str(), out_host, cap, n_total, st);
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64_t *offsets,
                                const int64_t *nsamp, const double *tsamp, const double *zmax,
                                int32_t nseries, double dz, int32_t numharm, double sigma,
                                fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream) {
+    FDAS_ENTRY_TRY
     TRY(check_plan(p));
     if (!series_dev || ((uintptr_t)series_dev & 7) || !offsets || !nsamp || !tsamp || !zmax)
         return p->fail(FDAS_E_INVAL, "NULL or misaligned argument");
@@ -1149,11 +1171,13 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
         << p->rec_cap;
     for (const auto &G : B.groups) key_group(key, G);
     return run_batch(p, series_dev, true, B, dz, numharm, key.str(), out_host, cap, n_total, st);
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, int32_t nchan, double tsamp,
                             double f0_mhz, double df_mhz, const fdas_dm_range *ranges, int32_t nranges,
                             float *out_dev, int64_t out_elems, void *stream) {
+    FDAS_ENTRY_TRY
     TRY(check_plan(p));
     if (!fil_dev || !out_dev || ((uintptr_t)out_dev & 3) || !ranges || nranges < 1 || nsamp < 1 || nchan < 1 ||
         nchan > 65535 || !(tsamp > 0) || !std::isfinite(tsamp) || !std::isfinite(f0_mhz) || !std::isfinite(df_mhz))
@@ -1294,6 +1318,7 @@ fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, 
     HIPTRY(p, hipStreamSynchronize(st));
     p->collect();
     return FDAS_OK;
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_refine_window(double r0, double z0, double dz, int32_t K, int64_t *k0, int32_t *m) {
@@ -1344,6 +1369,7 @@ fdas_status fdas_refine_grad(const float *spec_dev, int64_t spitch, int64_t nbin
 fdas_status fdas_refine(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries, double dz,
                         int32_t iters, fdas_refine_point *pts_host, float *power_host, int64_t n,
                         void *stream) {
+    FDAS_ENTRY_TRY
     TRY(check_plan(p));
     if (!series_dev || ((uintptr_t)series_dev & 7)) return p->fail(FDAS_E_INVAL, "series pointer NULL or misaligned");
     if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
@@ -1386,11 +1412,13 @@ fdas_status fdas_refine(fdas_plan p, const float *series_dev, int64_t nsamp, int
     std::memcpy(pts_host, p->h_rpts, (size_t)n * sizeof(fdas_refine_point));
     std::memcpy(power_host, p->h_rpow, (size_t)n * sizeof(float));
     return FDAS_OK;
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_plane(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
                        double tsamp, double zmax, double dz, float *plane_dev, int64_t plane_elems,
                        void *stream) {
+    FDAS_ENTRY_TRY
     Geometry g;
     TRY(check_common(p, series_dev, nsamp, nseries, tsamp, zmax, dz, g));
     if (!plane_dev || ((uintptr_t)plane_dev & 7) || plane_elems < (int64_t)nseries * g.NZ * g.NR)
@@ -1409,11 +1437,13 @@ fdas_status fdas_plane(fdas_plan p, const float *series_dev, int64_t nsamp, int3
     HIPTRY(p, hipStreamSynchronize(st));
     p->collect();
     return FDAS_OK;
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int32_t nseries,
                          double tsamp, double zmax, double dz, int32_t numharm, double sigma,
                          fdas_cand *out_host, int64_t cap, int64_t *n_total, void *stream) {
+    FDAS_ENTRY_TRY
     Geometry g;
     TRY(check_common(p, plane_dev, nsamp, nseries, tsamp, zmax, dz, g));
     TRY(check_search(p, numharm, sigma, out_host, cap, n_total));
@@ -1472,10 +1502,12 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
         drop_graph(p);
     }
     return p->fail(FDAS_E_DEVICE, "internal error: candidate capacity did not converge");
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
                           float *spec_dev, double *norm_host, void *stream) {
+    FDAS_ENTRY_TRY
     TRY(check_plan(p));
     if (!series_dev || ((uintptr_t)series_dev & 7) || !spec_dev || ((uintptr_t)spec_dev & 7))
         return p->fail(FDAS_E_INVAL, "device pointer NULL or not 8-byte aligned");
@@ -1503,6 +1535,7 @@ fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, i
     HIPTRY(p, hipStreamSynchronize(st));
     p->collect();
     return FDAS_OK;
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out) {
@@ -1520,6 +1553,7 @@ fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out) {
 }
 
 fdas_status fdas_tuning_export(fdas_plan p, char *buf, int64_t cap, int64_t *len) {
+    FDAS_ENTRY_TRY
     if (!p || !len || cap < 0 || (cap > 0 && !buf)) return FDAS_E_INVAL;
     std::ostringstream os;
     for (auto &kv : p->tuned)
@@ -1533,9 +1567,11 @@ fdas_status fdas_tuning_export(fdas_plan p, char *buf, int64_t cap, int64_t *len
         buf[n] = 0;
     }
     return (cap == 0 || cap > (int64_t)s.size()) ? FDAS_OK : FDAS_E_TRUNC;
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_tuning_import(fdas_plan p, const char *text) {
+    FDAS_ENTRY_TRY
     if (!p || !text) return FDAS_E_INVAL;
     std::istringstream is(text);
     std::string line;
@@ -1559,6 +1595,7 @@ fdas_status fdas_tuning_import(fdas_plan p, const char *text) {
     for (auto &kv : add) p->tuned[kv.first] = kv.second;
     drop_graph(p);
     return FDAS_OK;
+    FDAS_ENTRY_CATCH(plan_entry_error, p)
 }
 
 fdas_status fdas_profile_read(fdas_plan p, double *ms, int64_t *launches, int32_t reset) {

@@ -5,6 +5,9 @@
 
 #include <complex>
 #include <cstdint>
+#include <functional>
+#include <new>
+#include <stdexcept>
 #include <vector>
 
 #ifdef __HIPCC__
@@ -14,7 +17,30 @@
 #include <hip/hip_vector_types.h>
 #endif
 
+// Host exceptions (allocation failures, threads that cannot start) never
+// cross the C ABI: an entry point's body runs between these two macros and
+// such a failure becomes a status code (FDAS_E_NOMEM for allocations).
+#define FDAS_ENTRY_TRY try {
+#define FDAS_ENTRY_CATCH(handler, ctx)                                     \
+    }                                                                      \
+    catch (const std::bad_alloc &) {                                       \
+        return handler(ctx, FDAS_E_NOMEM, "host memory allocation failed"); \
+    }                                                                      \
+    catch (const std::exception &x) {                                      \
+        return handler(ctx, FDAS_E_DEVICE, x.what());                      \
+    }                                                                      \
+    catch (...) {                                                          \
+        return handler(ctx, FDAS_E_DEVICE, "unexpected host error");       \
+    }
+
 namespace fdas {
+
+// Runs fn(w) for w = 0..n-1 on up to n host threads, the caller's included.
+// Shares whose thread cannot be started run on the caller; an exception of fn
+// is caught in the thread that raised it. False if any share threw.
+bool run_parallel(int n, const std::function<void(int)> &fn);
+// entry-point error handler without a plan: the status alone
+inline fdas_status status_only(const void *, fdas_status s, const char *) { return s; }
 
 // ---------------------------------------------------------------- host FP64 math
 std::complex<double> fresnel(double x);

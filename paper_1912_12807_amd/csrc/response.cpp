@@ -227,6 +227,7 @@ void kernel_spectrum(double z, int parity, int K, int L, int mseg, float *out_in
 
 extern "C" fdas_status fdas_template_taps(double z, int32_t parity, int32_t K, double *re,
                                           double *im, int32_t cap, int32_t *ntaps, int32_t *d0) {
+    FDAS_ENTRY_TRY
     if (!ntaps || !d0 || (parity != 0 && parity != 1) || K < 0 || !std::isfinite(z))
         return FDAS_E_INVAL;
     std::vector<fdas::cd> taps;
@@ -240,4 +241,5 @@ extern "C" fdas_status fdas_template_taps(double z, int32_t parity, int32_t K, d
         im[i] = taps[i].imag();
     }
     return FDAS_OK;
+    FDAS_ENTRY_CATCH(fdas::status_only, nullptr)
 }

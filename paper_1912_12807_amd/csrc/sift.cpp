@@ -22,6 +22,7 @@
 
 extern "C" fdas_status fdas_sift(const fdas_cand *c, int64_t n, double tol_bins, int32_t max_ratio,
                                  fdas_sifted *out, int64_t cap, int64_t *n_out) {
+    FDAS_ENTRY_TRY
     if (n < 0 || (n > 0 && !c) || !(tol_bins >= 0) || !std::isfinite(tol_bins) || max_ratio < 1 ||
         max_ratio > 1024 || cap < 0 || (cap > 0 && !out) || !n_out)
         return FDAS_E_INVAL;
@@ -106,4 +107,5 @@ extern "C" fdas_status fdas_sift(const fdas_cand *c, int64_t n, double tol_bins,
         out[i].reserved = 0;
     }
     return cap >= (int64_t)alive.size() ? FDAS_OK : FDAS_E_TRUNC;
+    FDAS_ENTRY_CATCH(fdas::status_only, nullptr)
 }
