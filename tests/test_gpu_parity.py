@@ -222,6 +222,23 @@ def test_truncation_reports_true_count(fdas_gpu):
     assert total == len(full) and np.array_equal(whole, full)
 
 
+def test_results_of_earlier_calls_are_not_overwritten(fdas_gpu):
+    # every call returns records in storage of its own: a later search on the
+    # same plan (other data, other threshold, more records) leaves them intact
+    N = 1 << 13
+    plan = fdas_gpu.Plan(N, 2, 10.0, 2.0, 4)
+    x1, x2 = _cuda(_noise(2, N, 21)), _cuda(_noise(2, N, 22))
+    first = plan.search(x1, 1e-3, sigma=3.0)
+    kept = first.copy()
+    second = plan.search(x2, 1e-3, sigma=2.0)
+    part, _ = plan.search(x2, 1e-3, sigma=2.0, cap=5, allow_trunc=True)
+    assert len(second) > len(first) > 0
+    assert np.array_equal(first, kept)
+    assert np.array_equal(part, second[:5])
+    again = plan.search(x1, 1e-3, sigma=3.0)
+    assert np.array_equal(again, kept)
+
+
 def test_invalid_arguments_return_status(fdas_gpu):
     F = fdas_gpu
     N = 1 << 12
