@@ -198,6 +198,9 @@ struct BoundCfg {
 __device__ __forceinline__ float load_at(const bmax_t *base, uint32_t byte_off) {
     return half_bits_to_float(*reinterpret_cast<const bmax_t *>(reinterpret_cast<const char *>(base) + byte_off));
 }
+__device__ __forceinline__ uint16_t load_bits_at(const bmax_t *base, uint32_t byte_off) {
+    return *reinterpret_cast<const bmax_t *>(reinterpret_cast<const char *>(base) + byte_off);
+}
 
 template <int NH>
 __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ plane, int64_t pitch,
@@ -289,22 +292,63 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         const int kend = nblk - k0 < 64 ? nblk - k0 : 64;
         for (int kk = 0; kk < kend; ++kk) {
             const int32_t *fr = frange + (k0 + kk) * NH;
-            // both row blocks of every range (the same one twice when e = a):
-            // no branch, so no conversion can be placed where it would wait
-            // for all earlier loads
-            float B[SB][NH], C[SB][NH];
+            // Up to 8 harmonics: the first row block of every range, and the
+            // second only where the range has one (a wave-uniform test). The
+            // gathers keep their raw half bits, so no conversion sits in a
+            // branch where it would wait for all earlier loads, and both
+            // blocks' bits merge by an integer maximum (non-negative halves
+            // order like their bits). Above 8 harmonics that code holds too
+            // many registers, and both row blocks are gathered unconditionally
+            // (the same one twice when e = a).
+            float B[SB][NH];
             int wide = 0;
+            if constexpr (NH <= 8) {
+                uint16_t Bb[SB][NH], Cb[SB][NH];
+                // a zero the compiler cannot see through: with a literal 0 it
+                // folds the merge into the branch, where it waits for every
+                // earlier gather
+                const uint16_t zero = (uint16_t)__builtin_amdgcn_mbcnt_lo(0u, 0u);
 #pragma unroll
-            for (int j = 0; j < NH; ++j) {
-                const int32_t f = fr[j];
-                const int n = f >> 24;
-                wide |= n > 1;
-                const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
-                const uint32_t o1 = n > 0 ? o0 + rowb : o0;
+                for (int j = 0; j < NH; ++j) {
+                    const int32_t f = fr[j];
+                    const int n = f >> 24;
+                    wide |= n > 1;
+                    const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
+#pragma unroll
+                    for (int m = 0; m < SB; ++m) {
+                        Bb[m][j] = load_bits_at(yb[m], o0);
+                        Cb[m][j] = zero;
+                    }
+                    if (n > 0) {
+#pragma unroll
+                        for (int m = 0; m < SB; ++m) Cb[m][j] = load_bits_at(yb[m], o0 + rowb);
+                    }
+                }
 #pragma unroll
                 for (int m = 0; m < SB; ++m) {
-                    B[m][j] = load_at(yb[m], o0);
-                    C[m][j] = load_at(yb[m], o1);
+#pragma unroll
+                    for (int j = 0; j < NH; ++j)
+                        B[m][j] = half_bits_to_float(Bb[m][j] > Cb[m][j] ? Bb[m][j] : Cb[m][j]);
+                }
+            } else {
+                float C[SB][NH];
+#pragma unroll
+                for (int j = 0; j < NH; ++j) {
+                    const int32_t f = fr[j];
+                    const int n = f >> 24;
+                    wide |= n > 1;
+                    const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
+                    const uint32_t o1 = n > 0 ? o0 + rowb : o0;
+#pragma unroll
+                    for (int m = 0; m < SB; ++m) {
+                        B[m][j] = load_at(yb[m], o0);
+                        C[m][j] = load_at(yb[m], o1);
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < SB; ++m) {
+#pragma unroll
+                    for (int j = 0; j < NH; ++j) B[m][j] = fmaxf(B[m][j], C[m][j]);
                 }
             }
             if (wide) {
@@ -323,7 +367,7 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
 #pragma unroll
             for (int m = 0; m < SB; ++m) {
 #pragma unroll
-                for (int j = 0; j < NH; ++j) B[m][j] = ((need >> j) & 1u) ? fmaxf(B[m][j], C[m][j]) : 0.0f;
+                for (int j = 0; j < NH; ++j) B[m][j] = ((need >> j) & 1u) ? B[m][j] : 0.0f;
                 float U[NS];
                 stage_chain<NH>(B[m], U);
                 bool hot = false;
