@@ -241,6 +241,12 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
     for (int zi = z0; zi < z1; ++zi) {
         const __amdgpu_buffer_rsrc_t row_rs = __builtin_amdgcn_make_buffer_rsrc(
             out + (int64_t)zi * pitch, (short)0, 2 * g.Lv * (int)sizeof(float), kBufferRsrcWord3);
+        // up to L 2048 the parity-0 powers wait in registers and both
+        // parities of a bin are stored as one 8-byte pair (whole lines, half
+        // the store instructions); at L 4096 that would cost the registers of
+        // a wave, so each parity is stored as it is computed
+        constexpr bool kPairStore = L <= 2048;
+        float pw0[8];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             float2 v[8];
@@ -255,10 +261,19 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
             for (int q = 0; q < 8; ++q) {
                 const int i = t + q * T;
                 const float pw = __fmaf_rn(v[q].x, v[q].x, __fmul_rn(v[q].y, v[q].y));
-                if (i < g.Lv && ks + i < g.half)
+                if constexpr (kPairStore) {
+                    if (p == 0) {
+                        pw0[q] = pw;
+                    } else if (i < g.Lv && ks + i < g.half) {
+                        typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(pw0[q], pw)),
+                                                              row_rs, t_row, 2 * q * T * (int)sizeof(float), 0);
+                    }
+                } else if (i < g.Lv && ks + i < g.half) {
                     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, pw), row_rs,
                                                           t_row + p * (int)sizeof(float),
                                                           2 * q * T * (int)sizeof(float), 0);
+                }
                 if constexpr (PYR == 2) {
                     m0[q] = fmaxf(m0[q], pw);     // both parities: fused into 3-input maxima
                 } else if constexpr (PYR == 1) {
