@@ -6,12 +6,16 @@ normalisation, power plane, harmonic sums, thresholding, compaction, drift
 argmax and the copy of the candidate list to host memory. The float32 series
 are resident in HBM when the timed region starts. Prints ONE JSON line.
 
-Default workload: the FAST drift-scan shaped batch (128 series x 2^18
-samples at 0.2 ms, zmax 200, dz 2, numharm 8, sigma 6; 8 series carry pulse
-trains), the configuration the cells/s metric is quoted on.
+Default workload: the PMPS-shaped long-series batch (32 series x 2^23
+samples at 250 us, zmax 200, dz 2, numharm 16, sigma 6; binary-like pulse
+trains in 8 series and 50/100/150 Hz RFI tones in all), the largest
+single-GPU configuration of the benchmark set (5.39e10 cells per step).
+--config 2 runs the FAST drift-scan batch (128 x 2^18, numharm 8), whose
+figures the default run also reports under "fast_batch".
 
 Extra fields: "roofline" of the dominant kernel (device time per launch from
-HIP events recorded by the library on the search stream), "cpu_baseline" (the
+HIP events recorded by the library on the search stream; HBM roof at the
+plane's 4 bytes per cell, FP32 VALU fraction beside it), "cpu_baseline" (the
 FP64 oracle on a bounded sample, timed on the host cores), "plain_path" (the
 same kernels driven one series at a time) and "phases_ms".
 """
@@ -85,6 +89,46 @@ def _oracle_ragged_series(args):
     t0 = time.perf_counter()
     O.search_series(x, wl.tsamp[b], wl.zmax[b], wl.dz, wl.numharm, wl.sigma, series=b)
     return time.perf_counter() - t0
+
+
+def _oracle_window(args):
+    """Oracle time of every stage's maxima over W columns of one series of the
+    long-series batch (banded direct sums), excluding the series generation."""
+    config, b, W = args
+    import oracle as O
+    import synth
+    wl = _workload(config)
+    x = synth.generate(wl, [b])[0]
+    t0 = time.perf_counter()
+    Ah = O.normalise(O.spectrum(x))[0]
+    rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
+    lo = 2 * rlo * wl.numharm
+    ncand = 0
+    for H in O.stage_list(wl.numharm):
+        _, M, _ = O.band_maxima(Ah, rlo, wl.zmax, wl.dz, H, lo, lo + W)
+        ncand += int((M > O.threshold(H, wl.sigma)).sum())
+    return time.perf_counter() - t0, ncand
+
+
+def cpu_baseline_windows(config: int, wl, nz: int, cells_total: float, W: int = 1 << 18, max_cores: int = 16):
+    """The FP64 oracle on a bounded sample of the long-series batch: every stage's
+    maxima of W columns of each of up to 16 series, one process per series."""
+    import multiprocessing as mp
+    cores = max(1, min(max_cores, len(os.sched_getaffinity(0)), wl.nseries))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_window, [(config, b, W) for b in range(cores)])
+    wall = max(t for t, _ in res)
+    cells = cores * W * nz
+    value = cells / wall
+    return {"value": value, "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} of {wl.nseries} series, {W} contiguous columns each (from the start of the "
+                      f"stage-{wl.numharm} band) at all {nz} drift rows, every stage 1..{wl.numharm} with "
+                      f"thresholds (FP64 oracle: spectrum, median normalisation and banded direct tap sums of "
+                      f"the cells the harmonic sums read), one process per series; value = {cells:.3g} cells "
+                      f"/ {wall:.1f} s (the slowest process, generation excluded)",
+            "extrapolated_s_per_step": cells_total / value,
+            "cpu": _cpu_model()}
 
 
 def stream_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:
@@ -238,8 +282,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4, 5, 6, 7))
+    ap.add_argument("--config", type=int, default=3, choices=(1, 2, 3, 4, 5, 6, 7))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FAST-batch figures of the default run")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", type=int, default=0, choices=(0, 1),
                     help="time candidate launch parameters on the first search (during warmup)")
@@ -298,15 +343,83 @@ def main():
     if args.config in (6, 7):
         return bench_pipeline(args)
     wl = _workload(args.config)
+    popts = dict(seg_len=args.seg_len, harm_block=args.harm_block, harm_pair=args.harm_pair)
+    res = bench_batch(wl, args, popts, copy_calibration=args.copy_calibration)
+    x, cells, nr, nz = res.pop("_x"), res["cells"], res.pop("_nr"), res.pop("_nz")
+
+    plain = None
+    if not args.no_plain:
+        print("[bench] plain per-series path", file=sys.stderr, flush=True)
+        p1 = fdas.Plan(wl.nsamp, 1, wl.zmax, wl.dz, wl.numharm)
+        p1.search(x[0:1], wl.tsamp, sigma=wl.sigma, cap=1 << 22, allow_trunc=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(wl.nseries):
+            p1.search(x[b:b + 1], wl.tsamp, sigma=wl.sigma, cap=1 << 22, allow_trunc=True)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        plain = {"value": cells / pw, "unit": "cells/s", "ms_per_step": 1e3 * pw,
+                 "what": "same kernels, one series per fdas_search call"}
+        p1.close()
+    del x
+    torch.cuda.empty_cache()
+
+    extra = None
+    if args.config == 3 and not args.no_extra:
+        # the FAST drift-scan batch with the same code, reported beside the headline
+        wl2 = _workload(2)
+        r2 = bench_batch(wl2, args, {}, copy_calibration=False)
+        del r2["_x"], r2["_nr"], r2["_nz"]
+        extra = {"workload": wl2.name, "value": r2["value"], "unit": "cells/s", "ms_per_step": r2["ms_per_step"],
+                 "cells_per_step": r2["cells"], "roofline": r2["roofline"], "phases_ms": r2["phases_ms"],
+                 "candidates": r2["candidates"]}
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        if args.config == 3:
+            cpu = cpu_baseline_windows(args.config, wl, nz, cells)
+        else:
+            cpu = cpu_baseline(args.config, wl, nr, nz)
+
+    out = {
+        "metric": METRIC, "value": res["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "nseries": wl.nseries, "nsamp": wl.nsamp, "tsamp": wl.tsamp,
+                   "zmax": wl.zmax, "dz": wl.dz, "numharm": wl.numharm, "sigma": wl.sigma,
+                   "cells_per_step": cells, "seg_len": res["seg_len"], "tuning": res["tuning"],
+                   "parallelism": "single GPU"},
+        "roofline": res["roofline"],
+        "cpu_baseline": cpu,
+        "plain_path": plain,
+        "speedup_vs_plain": (res["value"] / plain["value"]) if plain else None,
+        "phases_ms": res["phases_ms"],
+        "candidates": res["candidates"],
+        "fast_batch": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(wl, args, popts, copy_calibration=False):
+    """Time args.steps searches of a fixed-length batch, then the per-phase kernel
+    times on a profiled plan with the same launch parameters; the roofline of the
+    dominant kernel."""
+    import numpy as np
+    import torch
+
+    import paper_1912_12807_amd as fdas
+    import synth
+
     print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
-    x = torch.from_numpy(synth.generate(wl)).cuda()
+    x = torch.from_numpy(synth.generate_parallel(wl)).cuda()
     rlo, nr, nz = fdas.geometry(wl.nsamp, wl.tsamp, wl.zmax, wl.dz)
     cells = wl.nseries * nr * nz
-    popts = dict(seg_len=args.seg_len, harm_block=args.harm_block, harm_pair=args.harm_pair)
     plan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, autotune=args.autotune, **popts)
     if args.tuning:
         plan.load_tuning(args.tuning.replace(";", "\n"))
-    if args.copy_calibration:
+    if copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
@@ -314,14 +427,14 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    print(f"[bench] {wl.name}: warmup {args.warmup}", file=sys.stderr, flush=True)
     # the long-series batch lists millions of candidates (RFI tones and their
     # harmonics): the copy-out keeps the first cap, every count is exact
     cap = 1 << 22
     for _ in range(args.warmup):
         cands, ncand = plan.search(x, wl.tsamp, sigma=wl.sigma, cap=cap, allow_trunc=True)
     torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] {wl.name}: timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -337,7 +450,7 @@ def main():
     # per-phase kernel times (HIP events on the search stream) from a plan with
     # the same launch parameters and profiling on, which runs every phase in
     # order on the one stream
-    print(f"[bench] phase timing {args.steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] {wl.name}: phase timing {args.steps} steps", file=sys.stderr, flush=True)
     pplan = fdas.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm, profile=1, **popts)
     if tuning:
         pplan.load_tuning(tuning)
@@ -351,29 +464,41 @@ def main():
     pplan.close()
     assert np.array_equal(pc, cands), "the profiled plan found other candidates"
 
-    # dominant kernel and its roofline
     phases = {k: v[0] / args.steps for k, v in prof.items()}
     dom = max(("plane", "harmsum"), key=lambda k: prof[k][0])
+    roof = roofline(wl, dom, prof, args.steps, info, rlo, nr, nz, cells)
+    return {"_x": x, "_nr": nr, "_nz": nz, "cells": cells, "value": value, "ms_per_step": ms_step,
+            "seg_len": info["seg_len"], "tuning": tuning or None, "roofline": roof,
+            "phases_ms": {k: round(v, 4) for k, v in phases.items()}, "candidates": int(ncand)}
+
+
+def roofline(wl, dom, prof, steps, info, rlo, nr, nz, cells):
+    """Roofline of the dominant kernel from its per-launch device time.
+
+    Plane (K4): the path's binding roof is HBM; the kernel's algorithmic bytes are
+    the 4-byte power of every cell it writes (the spectrum it reads is < 0.1 B per
+    cell). Its FP32 work per cell (inverse FFTs, template products and powers,
+    forward FFTs) is reported beside it against the vector peak.
+    Harmonic sums (K5): the half-precision block maxima read once and the stage
+    maxima written."""
     launches = max(1, prof[dom][1])
     t_launch = prof[dom][0] / 1e3 / launches           # s
-    per_launch = launches / args.steps                 # launches of the kernel per search
+    per_launch = launches / steps                      # launches of the kernel per search
     cells_launch = cells / per_launch
     L, mseg = info["seg_len"], info["mseg"]
-    Lv = L - 2 * mseg
     NS = int(math.log2(wl.numharm)) + 1
     if dom == "plane":
-        # overlap-save per (z row, parity, segment): inverse FFT 5 L log2 L, template product 6 L,
-        # power 3 L, over Lv outputs; plus one forward FFT per segment and z group (<= 8)
-        nseg = math.ceil((wl.nsamp // 2 - rlo) / Lv)
-        G = 1
-        while G < 8 and nz >= 2 * G * 12:
-            G *= 2
-        flops = (wl.nseries / per_launch) * nseg * (
-            2 * nz * (5 * L * math.log2(L) + 9 * L) + G * (5 * L * math.log2(L) + 2 * L))
-        achieved = flops / t_launch / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VECTOR_PEAK, "kernel": DOMINANT[dom],
-                "per_unit": f"{flops / cells_launch:.1f} FLOP/cell"}
+        byts = 4.0 * cells_launch
+        flops = plane_flops(wl.nseries / per_launch, wl.nsamp, rlo, nz, L, mseg)
+        alu = flops / t_launch / 1e12
+        achieved = byts / t_launch / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "kernel": DOMINANT[dom], "per_unit": "4 B/cell (plane write)",
+                "cells_per_launch": cells_launch,
+                "alu": {"achieved": alu, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+                        "frac": alu / FP32_VECTOR_PEAK, "per_unit": f"{flops / cells_launch:.1f} FLOP/cell",
+                        "nonpacked_peak": FP32_VECTOR_PEAK / 2,
+                        "frac_of_nonpacked": alu / (FP32_VECTOR_PEAK / 2)}}
     else:
         ser = wl.nseries / per_launch
         mp_ = (nr + 15) // 16 * 16
@@ -387,56 +512,15 @@ def main():
         achieved = byts / t_launch / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "kernel": DOMINANT[dom] if info["harm_blocks"] else "k_harmsum",
-                "per_unit": f"{byts / cells_launch:.3f} B/cell"}
+                "per_unit": f"{byts / cells_launch:.3f} B/cell", "cells_per_launch": cells_launch}
     roof["traffic"] = measured_traffic(dom, wl.name, L)
     roof["launch_ms"] = t_launch * 1e3
-    if roof["bound"] == "alu":
-        # all HIP code is built without packed FP32 instructions: half the quoted peak
-        roof["nonpacked_peak"] = FP32_VECTOR_PEAK / 2
-        roof["frac_of_nonpacked"] = roof["achieved"] / (FP32_VECTOR_PEAK / 2)
     roof["stream_copy_gbs"] = stream_copy_gbs()
-
-    plain = None
-    if not args.no_plain:
-        print("[bench] plain per-series path", file=sys.stderr, flush=True)
-        p1 = fdas.Plan(wl.nsamp, 1, wl.zmax, wl.dz, wl.numharm)
-        p1.search(x[0:1], wl.tsamp, sigma=wl.sigma, cap=1 << 20, allow_trunc=True)
-        torch.cuda.synchronize()
-        reps = 1
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            for b in range(wl.nseries):
-                p1.search(x[b:b + 1], wl.tsamp, sigma=wl.sigma, cap=1 << 20, allow_trunc=True)
-        torch.cuda.synchronize()
-        pw = time.perf_counter() - t0
-        plain = {"value": cells * reps / pw, "unit": "cells/s", "ms_per_step": 1e3 * pw / reps,
-                 "what": "same kernels, one series per fdas_search call"}
-        p1.close()
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.config, wl, nr, nz)
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wl.name, "nseries": wl.nseries, "nsamp": wl.nsamp, "tsamp": wl.tsamp,
-                   "zmax": wl.zmax, "dz": wl.dz, "numharm": wl.numharm, "sigma": wl.sigma,
-                   "cells_per_step": cells, "seg_len": L, "harm_block_rows": tuning.split()[4] if tuning else None,
-                   "tuning": tuning or None, "parallelism": "single GPU"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "plain_path": plain,
-        "speedup_vs_plain": (value / plain["value"]) if plain else None,
-        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
-        "candidates": int(ncand),
-    }
-    print(json.dumps(out), flush=True)
+    return roof
 
 
 def plane_flops(nseries, nsamp, rlo, nz, L, mseg):
+    # nseries may be fractional: the series share of one launch
     """Algorithmic FLOPs of the overlap-save plane: per (z row, parity, segment) an inverse
     FFT (5 L log2 L), the template product (6 L) and the power (3 L); per segment and z
     group one forward FFT and the scaling."""

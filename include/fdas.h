@@ -83,7 +83,11 @@ typedef struct {
                                     in a hipGraph and replay it when a call with the same input
                                     pointer and shapes repeats (sigma and offsets may change);
                                     ignored while profile is set */
-    int32_t reserved[4];         /* must be zero */
+    int32_t fail_alloc;          /* test hook: n > 0 makes the n-th device or pinned-host allocation made
+                                    for the plan (counted from fdas_plan_create on) fail as if memory
+                                    were exhausted, returning FDAS_E_NOMEM; the plan stays usable
+                                    (default 0: off) */
+    int32_t reserved[3];         /* must be zero */
 } fdas_plan_opts;
 
 /* One candidate. r = r_idx/2 and z = z_idx*dz are the Fourier frequency

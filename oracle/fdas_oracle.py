@@ -47,6 +47,7 @@ __all__ = [
     "normalise", "template", "plane", "plane_cells", "harmonic_index", "stage_list",
     "stage_maxima", "stage_sums_at", "gamma_sf", "log_gamma_sf", "threshold",
     "candidate_sigma", "search", "search_series", "CAND_FIELDS", "window_maxima",
+    "plane_band", "band_maxima",
 ]
 
 LN2 = math.log(2.0)
@@ -425,3 +426,63 @@ def window_maxima(Ah: np.ndarray, rlo: int, zmax: float, dz: float, H: int, R_lo
         S += vals[k * n:(k + 1) * n].reshape(Zq.shape[0], R.shape[0])
     a = np.argmax(S, axis=0)
     return R, S[a, np.arange(R.shape[0])], a - Z, S
+
+
+def plane_band(Ah: np.ndarray, R_lo: int, R_hi: int, zmax: float, dz: float, K: int = 16,
+               rows: Optional[Sequence[int]] = None) -> np.ndarray:
+    """P[zi][R - R_lo] for the columns R in [R_lo, R_hi) (half bins) and the z rows
+    zi = Zq + Zmax listed in rows (default: all; rows not listed stay 0).
+
+    The same definition as plane(): c(k0) = sum_d A^_{k0+d} t_d over the taps of
+    the trial (r = k0 + parity/2), bins outside [1, N/2 - 1] read as zero, each
+    tap sum a direct (non-FFT) correlation, on a column range only, so that it
+    works on series of any length.
+    """
+    half = Ah.shape[-1] - 1
+    Z = z_index_max(zmax, dz)
+    if R_hi <= R_lo:
+        return np.zeros((2 * Z + 1, 0))
+    k_lo, k_hi = R_lo >> 1, (R_hi - 1) >> 1              # trial bins k0 (inclusive)
+    pad = half_width(Z * dz, K) + 2
+    # spectrum bins k_lo - pad .. k_hi + pad, zero outside [1, N/2 - 1]
+    kk = np.arange(k_lo - pad, k_hi + pad + 1)
+    ok = (kk >= 1) & (kk <= half - 1)
+    seg = np.where(ok, Ah[np.clip(kk, 0, half)], 0.0).astype(np.complex128)
+    k0 = np.arange(k_lo, k_hi + 1)
+    out = np.zeros((2 * Z + 1, R_hi - R_lo), dtype=np.float64)
+    for zi in (range(2 * Z + 1) if rows is None else sorted(set(int(r) for r in rows))):
+        z = (zi - Z) * dz
+        for p in (0, 1):
+            d, t = template(z, p, K)
+            # c(k0) = sum_j seg[k0 - k_lo + pad + d_j] t_j: a direct correlation
+            lo = pad + int(d[0])
+            c = np.convolve(seg[lo:lo + k0.shape[0] + t.shape[0] - 1], t[::-1], mode="valid")
+            R = 2 * k0 + p
+            sel = (R >= R_lo) & (R < R_hi)
+            out[zi, R[sel] - R_lo] = c[sel].real ** 2 + c[sel].imag ** 2
+    return out
+
+
+def band_maxima(Ah: np.ndarray, rlo: int, zmax: float, dz: float, H: int, R_lo: int, R_hi: int,
+                K: int = 16, return_sums: bool = False):
+    """(R, M_H(R), Zq*) for the contiguous columns R in [R_lo, R_hi) of stage H
+    (and S_H[Zq + Zmax][R - R_lo] with return_sums).
+
+    S_H(R, Zq) = sum_{k=1..H} P(R_k, Zq_k) in the order k = 1..H, the plane cells
+    of harmonic k taken from plane_band over the columns [R_k(R_lo), R_k(R_hi - 1)]
+    and only the rows Zq_k that harmonic reads; Zq* is the smallest maximiser.
+    """
+    Z = z_index_max(zmax, dz)
+    R = np.arange(R_lo, R_hi, dtype=np.int64)
+    Zq = np.arange(-Z, Z + 1, dtype=np.int64)
+    S = np.zeros((Zq.shape[0], R.shape[0]), dtype=np.float64)
+    for k in range(1, H + 1):
+        Rk, _ = harmonic_index(R, 0, k, H)
+        _, Zk = harmonic_index(0, Zq, k, H)
+        lo, hi = int(Rk[0]), int(Rk[-1]) + 1
+        pb = plane_band(Ah, lo, hi, zmax, dz, K, rows=Zk + Z)
+        S += pb[(Zk + Z)[:, None], (Rk - lo)[None, :]]
+    a = np.argmax(S, axis=0)
+    if return_sums:
+        return R, S[a, np.arange(R.shape[0])], a - Z, S
+    return R, S[a, np.arange(R.shape[0])], a - Z

@@ -40,7 +40,7 @@ class PlanOpts(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("harm_order", ctypes.c_int32),
                 ("harm_bound", ctypes.c_int32), ("harm_block", ctypes.c_int32),
                 ("harm_pair", ctypes.c_int32), ("autotune", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("fail_alloc", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -76,7 +76,7 @@ def load(path: Optional[str] = None):
     global _lib
     if _lib is not None:
         return _lib
-    path = path or LIB_PATH
+    path = path or os.environ.get("FDAS_LIB_PATH") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1912_12807_amd.build.build()")
     lib = ctypes.CDLL(path)

@@ -22,6 +22,7 @@
 #include <functional>
 #include <list>
 #include <map>
+#include <memory>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -164,6 +165,8 @@ struct fdas_plan_s {
     bool sticky = false;
     uint64_t tick = 0;
     uint64_t call_tick = 0;     // tick at the start of the current call
+    int64_t n_alloc = 0;        // allocations made for the plan (the fail_alloc hook counts them)
+    int min_bz = 1;             // smallest drift block the block-maxima buffer was sized for
 
     std::list<Bank> banks;      // list: entries keep their address while others are evicted
     std::list<RowTable> tables;
@@ -295,13 +298,33 @@ struct fdas_plan_s {
 
 namespace {
 
+void drop_graph(fdas_plan p) {
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    if (p->graph_def) (void)hipGraphDestroy(p->graph_def);
+    p->graph = nullptr;
+    p->graph_def = nullptr;
+    p->graph_key.clear();
+}
+
+// The allocation hook of the plan option fail_alloc: the fail_alloc-th
+// allocation made for the plan fails as if memory were exhausted.
+bool injected_failure(fdas_plan p) {
+    ++p->n_alloc;
+    return p->opts.fail_alloc > 0 && p->n_alloc == p->opts.fail_alloc;
+}
+
+// (Re)allocate *ptr for count elements. The old buffer is freed first; on
+// failure *ptr is NULL. A captured graph holds buffer addresses, so any
+// (re)allocation drops it (the next graph call captures again).
 template <typename T>
 fdas_status dalloc(fdas_plan p, T **ptr, int64_t count, const char *what) {
+    drop_graph(p);
     if (*ptr) {
         (void)hipFree(*ptr);
         *ptr = nullptr;
     }
     if (count <= 0) count = 1;
+    if (injected_failure(p)) return p->fail(FDAS_E_NOMEM, std::string("injected allocation failure: ") + what);
     void *q = nullptr;
     hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
     if (e != hipSuccess) {
@@ -314,11 +337,13 @@ fdas_status dalloc(fdas_plan p, T **ptr, int64_t count, const char *what) {
 
 template <typename T>
 fdas_status halloc(fdas_plan p, T **ptr, int64_t count, const char *what) {
+    drop_graph(p);
     if (*ptr) {
         (void)hipHostFree(*ptr);
         *ptr = nullptr;
     }
     if (count <= 0) count = 1;
+    if (injected_failure(p)) return p->fail(FDAS_E_NOMEM, std::string("injected allocation failure: ") + what);
     void *q = nullptr;
     hipError_t e = hipHostMalloc(&q, (size_t)count * sizeof(T), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -329,12 +354,15 @@ fdas_status halloc(fdas_plan p, T **ptr, int64_t count, const char *what) {
     return FDAS_OK;
 }
 
-void drop_graph(fdas_plan p) {
-    if (p->graph) (void)hipGraphExecDestroy(p->graph);
-    if (p->graph_def) (void)hipGraphDestroy(p->graph_def);
-    p->graph = nullptr;
-    p->graph_def = nullptr;
-    p->graph_key.clear();
+// Grow a buffer whose capacity is tracked in *cap: the capacity is 0 while the
+// buffer is missing, so a failed allocation leaves the plan consistent (the
+// next call allocates again instead of using a freed pointer).
+template <typename T, typename C>
+fdas_status grow(fdas_plan p, T **ptr, C *cap, int64_t count, const char *what, bool host = false) {
+    *cap = 0;
+    TRY(host ? halloc(p, ptr, count, what) : dalloc(p, ptr, count, what));
+    *cap = (C)count;
+    return FDAS_OK;
 }
 
 // Evict the least recently used entry of a cache if it is full and that entry
@@ -483,11 +511,7 @@ fdas_status get_local(fdas_plan p, int64_t half, int nb, const int32_t **table, 
         *table = d;
         *nblk = (int)bs.size() - 1;
     }
-    if ((int64_t)*nblk * nb > p->lmed_cap) {
-        TRY(dalloc(p, &p->d_lmed, (int64_t)*nblk * nb, "block medians"));
-        p->lmed_cap = (int64_t)*nblk * nb;
-        drop_graph(p);
-    }
+    if ((int64_t)*nblk * nb > p->lmed_cap) TRY(grow(p, &p->d_lmed, &p->lmed_cap, (int64_t)*nblk * nb, "block medians"));
     return FDAS_OK;
 }
 
@@ -531,12 +555,18 @@ fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
     RowBlocks rb;
     TRY(get_rows(p, g.NZ, cg.zgroups, cfg.bz, numharm, cfg.pair != 0, rb));
     const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? pitch / 2 : pitch);
-    const bool bounded = !p->opts.harm_bound && bounded_table_bytes(rb.nblk, numharm) <= kBoundTableMax &&
-                         psstride <= kMaxPyrSeriesStride;
+    // K4 writes the block maxima whenever the buffer sized at plan creation
+    // holds those of a chunk series. The exhaustive sums do not read them, but
+    // every search then builds its plane with the same kernel instance, so that
+    // bounded and exhaustive searches return bit-identical records. When they
+    // do not fit, the plane is built without maxima (the chunk is then not
+    // limited by their buffer) and every cell is summed.
+    const bool with_pyr = psstride <= kMaxPyrSeriesStride && psstride <= p->pyr_cap;
+    const bool bounded = with_pyr && !p->opts.harm_bound && bounded_table_bytes(rb.nblk, numharm) <= kBoundTableMax;
     const int NS = nstages_of(numharm);
     const int64_t mpitch = round_up(g.NR, 16);
     int64_t chunk = std::min<int64_t>(p->plane_cap / sstride, p->maxv_cap / (NS * mpitch));
-    chunk = std::min<int64_t>(chunk, p->pyr_cap / psstride);
+    if (with_pyr) chunk = std::min<int64_t>(chunk, p->pyr_cap / psstride);
     if (chunk < 1) return p->fail(FDAS_E_INVAL, "one series' plane exceeds the workspace");
     p->last_harm_blocks = bounded ? rb.nblk : 0;
     p->last_harm_pair = rb.pair ? 1 : 0;
@@ -547,8 +577,8 @@ fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
         const int n = (int)std::min<int64_t>(chunk, nb - b0);
         hipEvent_t e = p->begin(st);
         HIPTRY(p, launch_corr_power(p->d_spec + (int64_t)(vbase + b0) * p->spitch, p->spitch,
-                                    p->d_scale + vbase + b0, bk.d, cg, n, p->d_plane, pitch, sstride, p->d_pyr,
-                                    psstride, rb, st));
+                                    p->d_scale + vbase + b0, bk.d, cg, n, p->d_plane, pitch, sstride,
+                                    with_pyr ? p->d_pyr : nullptr, psstride, rb, st));
         p->end(2, e, st);
         e = p->begin(st);
         if (bounded) {
@@ -589,7 +619,7 @@ fdas_status group_cfg(fdas_plan p, const Geometry &g, double zmax, double dz, in
     const int mseg = half_width(g.Z * dz, p->opts.K);
     const auto key = std::make_tuple(g.nsamp, g.Z, numharm);
     auto it = p->tuned.find(key);
-    if (it != p->tuned.end() && seg_len_ok(it->second.L, mseg) && it->second.bz >= 1) {
+    if (it != p->tuned.end() && seg_len_ok(it->second.L, mseg) && it->second.bz >= p->min_bz) {
         *out = it->second;
         return FDAS_OK;
     }
@@ -690,10 +720,7 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
         return FDAS_OK;
     }
     if (n > 0) {
-        if (n > p->h_rec_cap) {
-            TRY(halloc(p, &p->h_rec, n, "candidate staging"));
-            p->h_rec_cap = n;
-        }
+        if (n > p->h_rec_cap) TRY(grow(p, &p->h_rec, &p->h_rec_cap, n, "candidate staging", true));
         e = p->begin(st);
         HIPTRY(p, hipMemcpyAsync(p->h_rec, p->d_rec, n * sizeof(DevCand), hipMemcpyDeviceToHost, st));
         p->end(6, e, st);
@@ -854,9 +881,7 @@ fdas_status run_batch(fdas_plan p, const float *x, bool ragged, const Batch &B, 
         const fdas_status s = finish(p, B, dz, !ragged, out, cap, n_total, st, &regrow);
         if (!regrow) return s;
         const int64_t need = ragged ? p->h_state[0] : std::min<int64_t>(p->h_state[0], cap);
-        TRY(dalloc(p, &p->d_rec, need, "candidate records"));
-        p->rec_cap = need;
-        drop_graph(p);
+        TRY(grow(p, &p->d_rec, &p->rec_cap, need, "candidate records"));
     }
     return p->fail(FDAS_E_DEVICE, "internal error: candidate capacity did not converge");
 }
@@ -986,8 +1011,9 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     fdas_plan_opts o;
     fdas_plan_opts_default(&o);
     if (opts) o = *opts;
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (o.reserved[i]) return FDAS_E_INVAL;
+    if (o.fail_alloc < 0) return FDAS_E_INVAL;
     if (max_series < 1 || max_series > 65535 || !valid_numharm(numharm) || o.K < 1 || o.K > 1024 ||
         (o.norm != FDAS_NORM_MEDIAN && o.norm != FDAS_NORM_FIXED && o.norm != FDAS_NORM_LOCAL) ||
         (o.norm == FDAS_NORM_FIXED && !(o.fixed_var > 0)) || o.max_workspace_bytes < 0 ||
@@ -1001,16 +1027,16 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     const int mseg = half_width(g.Z * dz, o.K);
     if (!choose_L(mseg, o.seg_len)) return o.seg_len ? FDAS_E_INVAL : FDAS_E_UNSUPPORTED;
 
-    fdas_plan p = new (std::nothrow) fdas_plan_s;
+    // the guard destroys a half-built plan on every early return and on a host
+    // exception caught at the ABI boundary
+    std::unique_ptr<fdas_plan_s, void (*)(fdas_plan)> guard(new (std::nothrow) fdas_plan_s, fdas_plan_destroy);
+    fdas_plan p = guard.get();
     if (!p) return FDAS_E_NOMEM;
     p->opts = o;
     p->max_nsamp = max_nsamp;
     p->max_series = max_series;
     p->max_numharm = numharm;
-    auto bail = [&](fdas_status s) {
-        fdas_plan_destroy(p);
-        return s;
-    };
+    auto bail = [](fdas_status s) { return s; };
     if (hipGetDevice(&p->device) != hipSuccess) {
         (void)hipGetLastError();
         return bail(FDAS_E_DEVICE);
@@ -1051,6 +1077,7 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     // block maxima of every chunk series: blocks of >= kMinBlockRows rows
     // (NZ / bz + 8 blocks at most, z groups cut blocks), per column
     const int bzmin = o.harm_block ? o.harm_block : kMinBlockRows;
+    p->min_bz = bzmin;
     p->pyr_cap = chunk * (int64_t)(g.NZ / bzmin + 9) * pitch;
     if ((s = dalloc(p, &p->d_pyr, p->pyr_cap, "block maxima")) != FDAS_OK) return bail(s);
     const int NS = nstages_of(numharm);
@@ -1067,7 +1094,7 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     if ((s = halloc(p, &p->h_offs, max_series, "series offsets")) != FDAS_OK) return bail(s);
     p->h_rec_cap = 4096;
     if ((s = halloc(p, &p->h_rec, p->h_rec_cap, "candidate staging")) != FDAS_OK) return bail(s);
-    *out = p;
+    *out = guard.release();
     return FDAS_OK;
     FDAS_ENTRY_CATCH(plan_entry_error, nullptr)
 }
@@ -1252,8 +1279,10 @@ fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, 
             ntab += (int64_t)nchan * npad[r];
         }
         if (ntab > p->delays_cap) {
-            TRY(dalloc(p, &p->d_delays, ntab, "delay tables"));
-            TRY(halloc(p, &p->h_delays, ntab, "delay tables"));
+            int64_t hcap = 0;
+            TRY(grow(p, &p->d_delays, &p->delays_cap, ntab, "delay tables"));
+            p->delays_cap = 0;
+            TRY(grow(p, &p->h_delays, &hcap, ntab, "delay tables", true));
             p->delays_cap = ntab;
         }
         {
@@ -1271,12 +1300,14 @@ fdas_status fdas_dedisperse(fdas_plan p, const uint8_t *fil_dev, int64_t nsamp, 
     const std::vector<int> &group = p->dd_group, &span = p->dd_span, &npad = p->dd_npad;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (rows_max * nchan > p->dd_cap) {
-        TRY(dalloc(p, &p->d_dd[0], rows_max * nchan, "dedispersion rows"));
+        TRY(grow(p, &p->d_dd[0], &p->dd_cap, rows_max * nchan, "dedispersion rows"));
+        p->dd_cap = 0;
         TRY(dalloc(p, &p->d_dd[1], rows_max * nchan, "dedispersion rows"));
         p->dd_cap = rows_max * nchan;
     }
     if (nchan > p->cpad_cap) {
-        TRY(dalloc(p, &p->d_csum, nchan, "channel sums"));
+        TRY(grow(p, &p->d_csum, &p->cpad_cap, nchan, "channel sums"));
+        p->cpad_cap = 0;
         TRY(dalloc(p, &p->d_cpad, nchan, "channel means"));
         p->cpad_cap = nchan;
     }
@@ -1392,7 +1423,8 @@ fdas_status fdas_refine(fdas_plan p, const float *series_dev, int64_t nsamp, int
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (n > p->rpts_cap) {
-        TRY(dalloc(p, &p->d_rpts, n, "refinement points"));
+        TRY(grow(p, &p->d_rpts, &p->rpts_cap, n, "refinement points"));
+        p->rpts_cap = 0;
         TRY(dalloc(p, &p->d_rpow, n, "refinement powers"));
         TRY(halloc(p, &p->h_rpts, n, "refinement points"));
         TRY(halloc(p, &p->h_rpow, n, "refinement powers"));
@@ -1497,9 +1529,7 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
         bool regrow = false;
         const fdas_status s = finish(p, B, dz, true, out_host, cap, n_total, st, &regrow);
         if (!regrow) return s;
-        TRY(dalloc(p, &p->d_rec, std::min<int64_t>(p->h_state[0], cap), "candidate records"));
-        p->rec_cap = std::min<int64_t>(p->h_state[0], cap);
-        drop_graph(p);
+        TRY(grow(p, &p->d_rec, &p->rec_cap, std::min<int64_t>(p->h_state[0], cap), "candidate records"));
     }
     return p->fail(FDAS_E_DEVICE, "internal error: candidate capacity did not converge");
     FDAS_ENTRY_CATCH(plan_entry_error, p)
@@ -1586,6 +1616,9 @@ fdas_status fdas_tuning_import(fdas_plan p, const char *text) {
             !valid_numharm(nh) || !pow2(L) || L < 512 || L > 4096 || bz < 1 || bz > 64 ||
             (harm_pair != 0 && harm_pair != 1))
             return p->fail(FDAS_E_INVAL, "malformed tuning line: " + line);
+        if (bz < p->min_bz)
+            return p->fail(FDAS_E_INVAL, "tuning line with fewer drift rows per block than the plan's block-maxima "
+                                         "buffer allows (" + std::to_string(p->min_bz) + "): " + line);
         LaunchCfg c;
         c.L = L;
         c.bz = bz;

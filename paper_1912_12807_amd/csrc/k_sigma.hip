@@ -1,77 +1,82 @@
-// Significance of every candidate record, in FP64 on the device.
+// Significance of every candidate record, in FP32 on the device.
 //
-// The same arithmetic as the host functions of the detection statistics: a
-// stage-H sum S of unit-exponential powers has the Gamma(H, 1) survival
+// A stage-H sum S of unit-exponential powers has the Gamma(H, 1) survival
 // Q(H, S) = exp(-S) sum_{j<H} S^j / j!, and the reported sigma is the s whose
 // Gaussian upper tail erfc(s / sqrt 2) / 2 equals Q, found in log space by
-// safeguarded Newton steps. Running it here keeps long candidate lists (many
-// trial DMs at a low threshold) from spending most of a search on the host.
+// safeguarded Newton steps (the same formulation as the host FP64 statistics,
+// evaluated here in single precision).
+//
+// Error against the host FP64 value: log Q carries an absolute rounding error
+// of about ulp(S) (the -S term dominates for strong signals), and d sigma /
+// d log Q is about -1/sigma, so sigma is off by about ulp(S)/sigma ~ 1e-7 sigma
+// (S ~ sigma^2 / 2); below sigma ~ 25 the erfc evaluation adds a few ulp. The
+// records are therefore within 1e-5 (relative, or absolute below 1) of the
+// host statistics, which the tests check over all stages and over powers up to
+// the 10^6 of strong RFI tones. Thresholds, which decide candidates, stay FP64
+// on the host (rounded once to FP32 for the comparison on the device).
 #include "fdas_internal.h"
 
 namespace fdas {
 
-__device__ static double dev_log_gamma_sf(int H, double S) {
-    if (S <= 0.0) return 0.0;
-    const double ls = log(S);
-    if (S < H) {
+// log Q(H, S)
+__device__ static float sf_log_gamma(int H, float S) {
+    if (S <= 0.0f) return 0.0f;
+    const float ls = logf(S);
+    if (S < (float)H) {
         // below the mean: log1p of minus the lower tail exp(-S) sum_{j>=H} S^j / j!
-        double term = 1.0, acc = 1.0;
-        for (int j = H + 1; j < H + 400; ++j) {
-            term *= S / j;
+        // (terms scaled by S^H / H!, each the previous times S / j)
+        float term = 1.0f, acc = 1.0f;
+        for (int j = H + 1; j < H + 200; ++j) {
+            term *= S / (float)j;
             acc += term;
-            if (term < 1e-17 * acc) break;
+            if (term < 1e-8f * acc) break;
         }
-        return log1p(-exp(-S + H * ls - lgamma(H + 1.0) + log(acc)));
+        return log1pf(-expf(-S + (float)H * ls - lgammaf((float)H + 1.0f) + logf(acc)));
     }
     // the H terms scaled by the largest (j = H - 1), each the next times j / S
-    double acc = 1.0, r = 1.0;
+    float acc = 1.0f, r = 1.0f;
     for (int j = H - 1; j > 0; --j) {
-        r *= j / S;
+        r *= (float)j / S;
         acc += r;
     }
-    return -S + ((H - 1) * ls - lgamma((double)H)) + log(acc);
+    return -S + ((float)(H - 1) * ls - lgammaf((float)H)) + logf(acc);
 }
 
-__device__ static double dev_log_gauss_tail(double s) {
-    constexpr double kLogSqrt2Pi = 0.91893853320467274178;   // log sqrt(2 pi)
-    if (s < 0.0) return log1p(-0.5 * erfc(-s * 0.70710678118654752440));
-    if (s < 25.0) return log(0.5 * erfc(s * 0.70710678118654752440));
-    // asymptotic series of the Mills ratio
-    const double inv2 = 1.0 / (s * s);
-    double term = 1.0, sum = 1.0;
-    for (int n = 1; n < 30; ++n) {
-        const double nt = -term * (2.0 * n - 1.0) * inv2;
-        if (fabs(nt) > fabs(term)) break;
+// log(erfc(s / sqrt 2) / 2)
+__device__ static float sf_log_gauss_tail(float s) {
+    constexpr float kLogSqrt2Pi = 0.918938533f;   // log sqrt(2 pi)
+    constexpr float kInvSqrt2 = 0.707106781f;
+    if (s < 0.0f) return log1pf(-0.5f * erfcf(-s * kInvSqrt2));
+    if (s < 9.0f) return logf(0.5f * erfcf(s * kInvSqrt2));
+    // asymptotic series of the Mills ratio: tail = phi(s)/s sum (-1)^n (2n-1)!! / s^(2n)
+    const float inv2 = 1.0f / (s * s);
+    float term = 1.0f, sum = 1.0f;
+    for (int n = 1; n < 20; ++n) {
+        const float nt = -term * (2.0f * n - 1.0f) * inv2;
+        if (fabsf(nt) > fabsf(term)) break;
         term = nt;
         sum += term;
-        if (fabs(term) < 1e-18) break;
+        if (fabsf(term) < 1e-9f) break;
     }
-    return -0.5 * s * s - log(s) - kLogSqrt2Pi + log(sum);
+    return -0.5f * s * s - logf(s) - kLogSqrt2Pi + logf(sum);
 }
 
-__device__ static double dev_sigma(int H, double power) {
-    constexpr double kPi = 3.14159265358979323846;
-    constexpr double kLogSqrt2Pi = 0.91893853320467274178;
-    const double lq = dev_log_gamma_sf(H, power);
-    double s = (lq < -1.0) ? sqrt(fmax(0.0, -2.0 * lq - log(-4.0 * kPi * lq))) : 0.0;
-    double lo = -40.0, hi = 1e5;
-    bool close = false;
-    for (int it = 0; it < 200; ++it) {
-        const double lt = dev_log_gauss_tail(s);
-        const double g = lt - lq;
-        if (g > 0) lo = s; else hi = s;
-        const double d = -exp(-0.5 * s * s - kLogSqrt2Pi - lt);
-        double sn = s - g / d;
-        const bool newton = sn > lo && sn < hi;
-        if (close) {
-            if (newton) s = sn;
-            break;
-        }
-        if (!newton) sn = 0.5 * (lo + hi);
-        const double step = fabs(sn - s);
+__device__ static float sf_sigma(int H, float power) {
+    constexpr float kPi = 3.14159265f;
+    constexpr float kLogSqrt2Pi = 0.918938533f;
+    const float lq = sf_log_gamma(H, power);
+    float s = (lq < -1.0f) ? sqrtf(fmaxf(0.0f, -2.0f * lq - logf(-4.0f * kPi * lq))) : 0.0f;
+    float lo = -40.0f, hi = 1e5f;
+    for (int it = 0; it < 100; ++it) {
+        const float lt = sf_log_gauss_tail(s);
+        const float g = lt - lq;              // decreasing in s
+        if (g > 0.0f) lo = s; else hi = s;
+        const float d = -expf(-0.5f * s * s - kLogSqrt2Pi - lt);
+        float sn = s - g / d;
+        if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
+        const float step = fabsf(sn - s);
         s = sn;
-        if (step <= 1e-14 * fmax(1.0, fabs(s))) break;
-        close = newton && step <= 1e-7 * fmax(1.0, fabs(s));
+        if (step <= 2e-7f * fmaxf(1.0f, fabsf(s)) || hi - lo <= 2e-7f * fmaxf(1.0f, fabsf(s))) break;
     }
     return s;
 }
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(256) void k_cand_sigma(DevCand *__restrict__ rec, c
                                                     int64_t cap) {
     const int64_t end = state[0] < cap ? state[0] : cap;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < end; i += (int64_t)gridDim.x * 256)
-        rec[i].sigma = dev_sigma(1 << rec[i].s, (double)rec[i].power);
+        rec[i].sigma = (double)sf_sigma(1 << rec[i].s, rec[i].power);
 }
 
 hipError_t launch_cand_sigma(DevCand *rec, const int64_t *state, int64_t cap, hipStream_t st) {

@@ -265,6 +265,33 @@ def generate(wl: Workload, series_idx=None) -> np.ndarray:
     return _render(wl, list(series_idx))
 
 
+def _render_one(args):
+    wl, b = args
+    return _render(wl, [b])[0]
+
+
+def generate_parallel(wl: Workload, series_idx=None, workers: int = 16) -> np.ndarray:
+    """generate() with the series drawn in up to `workers` processes (same bytes: each
+    series has its own seeded stream). For the long-series batches, whose serial
+    generation takes tens of seconds."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    idx = list(range(wl.nseries)) if series_idx is None else list(series_idx)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    nw = max(1, min(workers, avail, len(idx)))
+    if nw == 1:
+        return generate(wl, idx)
+    out = np.empty((len(idx), wl.nsamp), dtype=np.float32)
+    with cf.ProcessPoolExecutor(nw, mp_context=mp.get_context("spawn")) as ex:
+        for row, x in enumerate(ex.map(_render_one, [(wl, b) for b in idx])):
+            out[row] = x
+    return out
+
+
 def small_batch(nseries: int, nsamp: int, tsamp: float, zmax: float, dz: float, numharm: int,
                 sigma: float = 6.0, config: int = 90, signals: int = 2, zabs_max: float = None,
                 amp_range=(0.05, 0.5), noise: bool = True) -> Workload:

@@ -36,7 +36,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol(F):
     syms = declared_symbols()
     assert len(syms) >= 15
-    lib = ctypes.CDLL(F.LIB_PATH)
+    lib = F.load()       # the library the binding loaded (a sanitized build under test_sanitize_cpu)
     for s in syms:
         assert hasattr(lib, s), s
     assert set(syms) == set(F.EXPORTED)
@@ -114,4 +114,21 @@ def test_plan_create_rejects_bad_arguments_before_touching_a_device(F):
         assert not h.value
     o.reserved[0] = 1
     assert lib.fdas_plan_create(ctypes.byref(h), 1 << 12, 1, 10.0, 2.0, 1, ctypes.byref(o)) == F.FDAS_E_INVAL
+    o = F.default_opts(fail_alloc=-1)
+    assert lib.fdas_plan_create(ctypes.byref(h), 1 << 12, 1, 10.0, 2.0, 1, ctypes.byref(o)) == F.FDAS_E_INVAL
     assert lib.fdas_plan_create(ctypes.byref(h), 3000, 1, 10.0, 2.0, 1, None) == F.FDAS_E_UNSUPPORTED
+    assert not h.value
+
+
+def test_plan_create_past_the_argument_checks_without_a_device(F):
+    """Valid arguments on a machine without a GPU: the half-built plan is released
+    and the call reports a device error (run under the sanitizers by
+    test_sanitize_cpu, which would flag a use after free or double free)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    lib = F.load()
+    h = ctypes.c_void_p()
+    for _ in range(3):
+        assert lib.fdas_plan_create(ctypes.byref(h), 1 << 12, 2, 10.0, 2.0, 4, None) == F.FDAS_E_DEVICE
+        assert not h.value

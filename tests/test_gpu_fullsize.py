@@ -2,9 +2,12 @@
 
 The batch is searched exactly as the benchmark does (same plan options, one
 launch per kernel). The oracle checks what it can compute at these sizes:
-complete candidate lists of selected series (FFT-convolution oracle), every
-GPU candidate by directly evaluated plane cells, random non-candidate columns,
-sampled plane cells, and recovery of the injected signals.
+complete candidate lists of selected series (FFT-convolution oracle), complete
+candidate sets of contiguous column windows of every stage (banded direct
+sums: the start of each stage's band, the columns whose harmonic sums read the
+RFI tones or an injected pulsar, random windows), every GPU candidate (or a
+sample of them where the list runs to a million) by directly evaluated plane
+cells, sampled plane cells, and recovery of the injected signals.
 """
 import numpy as np
 import pytest
@@ -66,6 +69,72 @@ def _non_candidates(cands, x_of, wl, series, n=40, seed=1):
             assert np.all(M <= T * (1 + REL)), (b, H, np.max(M), T)
 
 
+def _stage_windows(wl, b, H, W=4096, halo=1024, seed=0):
+    """Contiguous column windows [lo, hi) of stage H on series b, clipped to the
+    stage's band and merged: its first W columns, +-halo columns around the
+    columns whose H-harmonic sums read an RFI tone (as harmonic H, H/2 or 1) or
+    the H-th harmonic of a pulsar injected in b, and two random W-column windows."""
+    rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
+    band_lo, N = 2 * rlo * H, wl.nsamp
+    wins = [(band_lo, band_lo + W)]
+    for inj in wl.injections:
+        if inj.kind == "tone" or (inj.kind == "sine" and inj.series in (b, -1)):
+            for k in sorted({H, max(1, H // 2), 1}):
+                c = int(round(2 * inj.r0 * H / k))
+                wins.append((c - halo, c + halo))
+        elif inj.kind == "pulse" and inj.series == b:
+            c = int(round(2 * inj.r0 * H))
+            wins.append((c - halo, c + halo))
+    rng = np.random.default_rng(seed * 97 + H)
+    for _ in range(2):
+        s0 = int(rng.integers(band_lo, N - W))
+        wins.append((s0, s0 + W))
+    out = []
+    for lo, hi in sorted((max(lo, band_lo), min(hi, N)) for lo, hi in wins):
+        if hi <= lo:
+            continue
+        if out and lo <= out[-1][1]:
+            out[-1] = (out[-1][0], max(out[-1][1], hi))
+        else:
+            out.append((lo, hi))
+    return out
+
+
+def _windows_match(cands, x_of, wl, series, W=4096, halo=1024):
+    """Complete candidate sets of every stage's windows (_stage_windows) against the
+    oracle's banded sums, in both directions, under the comparison rule (keys may
+    differ only where the oracle maximum lies within 1e-4 of the threshold)."""
+    rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
+    Z = O.z_index_max(wl.zmax, wl.dz)
+    stats = {"columns": 0, "candidates": 0, "banded": 0}
+    for b in series:
+        Ah = _ah((wl.name, b), x_of(b))
+        mine_b = cands[cands["series"] == b]
+        for H in O.stage_list(wl.numharm):
+            T = O.threshold(H, wl.sigma)
+            mine_h = mine_b[mine_b["harm"] == H]
+            for lo, hi in _stage_windows(wl, b, H, W, halo, seed=b):
+                R, M, Zs, S = O.band_maxima(Ah, rlo, wl.zmax, wl.dz, H, lo, hi, return_sums=True)
+                sel = mine_h[(mine_h["r_idx"] >= lo) & (mine_h["r_idx"] < hi)]
+                g = {int(c["r_idx"]): (int(c["z_idx"]), float(c["power"])) for c in sel}
+                assert len(g) == len(sel), (b, H, lo, "duplicate columns")
+                o = set(int(r) for r in R[M > T])
+                for r in set(g) ^ o:
+                    i = r - lo
+                    side = "gpu only" if r in g else "oracle only"
+                    assert abs(M[i] - T) <= REL * T, (side, b, H, r, M[i], T, g.get(r))
+                    stats["banded"] += 1
+                for r in set(g) & o:
+                    i = r - lo
+                    zg, pg = g[r]
+                    assert abs(pg - M[i]) <= REL * max(M[i], 1.0), (b, H, r, pg, M[i])
+                    if zg != Zs[i]:
+                        assert S[zg + Z, i] >= M[i] * (1 - REL), (b, H, r, zg, Zs[i])
+                stats["columns"] += hi - lo
+                stats["candidates"] += len(o)
+    return stats
+
+
 def _sampled_plane(plane_cpu, x_of, wl, series, n=1500, seed=2):
     rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
     Z = O.z_index_max(wl.zmax, wl.dz)
@@ -110,8 +179,16 @@ def test_fast_batch_full_candidate_lists_of_two_series(fast):
 def test_fast_batch_every_candidate_verified(fast):
     wl, x, _, _, cands = fast
     assert len(cands) > 50
-    n = _verify_candidates(cands, lambda b: x[b], wl, max_check=60)
-    assert n >= 50
+    n = _verify_candidates(cands, lambda b: x[b], wl)
+    assert n == len(cands)
+
+
+def test_fast_batch_stage_windows_complete(fast):
+    wl, x, _, _, cands = fast
+    carriers = sorted({i.series for i in wl.injections})
+    st = _windows_match(cands, lambda b: x[b], wl, series=[carriers[0], carriers[-1], 77])
+    print("FAST batch windows:", st)
+    assert st["candidates"] > 0
 
 
 def test_fast_batch_random_columns_are_not_candidates(fast):
@@ -145,17 +222,32 @@ def test_fast_batch_injected_pulsars_found(fast):
 def pmps(fdas_gpu):
     import torch
     wl = synth.config3()
-    x = synth.generate(wl)
+    x = synth.generate_parallel(wl)
     xd = torch.from_numpy(x).cuda()
     plan = fdas_gpu.Plan(wl.nsamp, wl.nseries, wl.zmax, wl.dz, wl.numharm)
     cands = plan.search(xd, wl.tsamp, sigma=wl.sigma, cap=1 << 21)
     return wl, x, xd, plan, cands
 
 
-def test_pmps_every_candidate_verified(pmps):
+def test_pmps_sampled_candidates_verified(pmps):
+    # 1.2 million records: a seeded sample of 12 per (series, stage) is evaluated
+    # cell by cell; the window test below checks complete sets
     wl, x, _, _, cands = pmps
     assert len(cands) > 50
     _verify_candidates(cands, lambda b: x[b], wl, max_check=12)
+
+
+def test_pmps_stage_windows_complete(pmps):
+    # complete candidate sets, both directions, on contiguous windows of every stage
+    # of a pulsar carrier and a series without a pulsar: band starts, the columns
+    # whose sums read the 50/100/150 Hz tones (as harmonic H, H/2 or 1) or the
+    # pulsar's H-th harmonic, and random windows
+    wl, x, _, _, cands = pmps
+    carrier = max((i for i in wl.injections if i.kind == "pulse"), key=lambda i: i.amp).series
+    quiet = next(b for b in range(wl.nseries) if b not in {i.series for i in wl.injections})
+    st = _windows_match(cands, lambda b: x[b], wl, series=[carrier, quiet])
+    print("PMPS windows:", st)
+    assert st["columns"] > 200000 and st["candidates"] > 10000
 
 
 def test_pmps_random_columns_are_not_candidates(pmps):

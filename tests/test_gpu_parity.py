@@ -144,7 +144,7 @@ def test_search_noise_free_fixed_norm_three_candidates(fdas_gpu):
     g = plan.search(_cuda(x), wl.tsamp, sigma=6.0)
     assert [(int(c["r_idx"]), int(c["z_idx"])) for c in g] == [(20000, 4), (20001, 4), (20003, 1)]
     assert g["power"][1] == pytest.approx(70.258485, rel=1e-4)
-    assert g["sigma"][1] == pytest.approx(O.candidate_sigma(1, g["power"][1]), rel=1e-9)
+    assert g["sigma"][1] == pytest.approx(O.candidate_sigma(1, g["power"][1]), rel=1e-5)
     assert g["f_hz"][1] == pytest.approx(10000.5 / (wl.nsamp * wl.tsamp), rel=1e-12)
     assert g["fdot_hz_s"][1] == pytest.approx(8.0 / (wl.nsamp * wl.tsamp) ** 2, rel=1e-12)
 
@@ -186,18 +186,28 @@ def test_search_chunked_workspace_matches_unchunked(fdas_gpu):
 
 # ----------------------------------------------------------------------------- edge cases
 
+# bound of the FP32 device significance against the FP64 host statistics
+SIGMA_TOL = 1e-5
+
+
 def test_device_significance_equals_host_statistics(fdas_gpu):
-    """Record sigmas are computed on the device in FP64; they agree with the host
-    statistics (and so with the oracle's reading) for every stage."""
-    B, N, ts, zmax, dz, nh = 2, 1 << 14, 1e-3, 20.0, 2.0, 32
+    """Record sigmas are computed on the device in FP32; they agree with the FP64
+    host statistics (and so with the oracle's reading) within 1e-5 (relative, or
+    absolute below 1) for every stage, from powers just above a low threshold to
+    the 10^5-10^6 of strong tones."""
+    B, N, ts, zmax, dz, nh = 3, 1 << 14, 1e-3, 20.0, 2.0, 32
     wl = synth.small_batch(B, N, ts, zmax, dz, nh, config=99, signals=2, amp_range=(0.3, 3.0))
-    x = _cuda(synth.generate(wl))
-    c = fdas_gpu.Plan(N, B, zmax, dz, nh).search(x, ts, sigma=2.5, cap=1 << 20)
+    x = synth.generate(wl)
+    # a strong on-bin tone in the last series: powers near N a^2 / 4 = 1.5e5
+    x[2] += (6.0 * np.cos(2 * np.pi * 1234.0 * np.arange(N) / N)).astype(np.float32)
+    c = fdas_gpu.Plan(N, B, zmax, dz, nh).search(_cuda(x), ts, sigma=2.5, cap=1 << 20)
     assert len(c) > 1000 and len(set(c["harm"].tolist())) == 6
+    assert c["power"].max() > 1e5
     host = np.array([fdas_gpu.sigma_of(int(h), float(p)) for h, p in zip(c["harm"], c["power"])])
-    np.testing.assert_allclose(c["sigma"], host, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(c["sigma"], host, rtol=SIGMA_TOL, atol=SIGMA_TOL)
     for i in np.linspace(0, len(c) - 1, 25).astype(int):
-        assert c["sigma"][i] == pytest.approx(O.candidate_sigma(int(c["harm"][i]), float(c["power"][i])), rel=1e-9)
+        ref = O.candidate_sigma(int(c["harm"][i]), float(c["power"][i]))
+        assert c["sigma"][i] == pytest.approx(ref, rel=SIGMA_TOL, abs=SIGMA_TOL)
 
 
 def test_zero_series_give_no_candidates(fdas_gpu):

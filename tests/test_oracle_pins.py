@@ -384,6 +384,41 @@ def test_window_maxima_match_full_search():
         assert np.array_equal(Zw, Zs[i0:i0 + 40])
 
 
+def test_plane_band_matches_full_plane_including_band_edges():
+    # the banded direct sums equal the full plane column for column, also where the
+    # taps run past bin 1 or bin N/2 - 1 and for a band that starts on an odd column
+    N = 1 << 11
+    Ah = _noise_spectrum(N, 14)
+    rlo, zmax, dz = 3, 12.0, 2.0
+    pl = O.plane(Ah, rlo, zmax, dz)
+    for lo, hi in ((2 * rlo, 2 * rlo + 50), (2 * rlo + 7, 900), (N - 41, N)):
+        pb = O.plane_band(Ah, lo, hi, zmax, dz)
+        assert np.max(np.abs(pb - pl[:, lo - 2 * rlo:hi - 2 * rlo])) <= 1e-12
+    Z = O.z_index_max(zmax, dz)
+    rows = [0, 3, 2 * Z]
+    pb = O.plane_band(Ah, 101, 333, zmax, dz, rows=rows)
+    assert np.max(np.abs(pb[rows] - pl[rows, 101 - 2 * rlo:333 - 2 * rlo])) <= 1e-12
+    assert not np.any(np.delete(pb, rows, axis=0))
+
+
+def test_band_maxima_match_full_search():
+    wl = synth.small_batch(1, 1 << 12, 1e-3, 10.0, 2.0, 8, config=92, signals=1,
+                           amp_range=(0.3, 0.5))
+    x = synth.generate(wl)[0]
+    rlo = O.rlo_bins(wl.nsamp, wl.tsamp)
+    Ah, _ = O.normalise(O.spectrum(x))
+    pl = O.plane(Ah, rlo, wl.zmax, wl.dz)
+    Z = O.z_index_max(wl.zmax, wl.dz)
+    for H in (1, 2, 4, 8):
+        R, M, Zs = O.stage_maxima(pl, rlo, Z, H, wl.nsamp)
+        for lo, hi in ((2 * rlo * H, 2 * rlo * H + 64), (2 * rlo * H + 333, wl.nsamp)):
+            Rb, Mb, Zb = O.band_maxima(Ah, rlo, wl.zmax, wl.dz, H, lo, hi)
+            i0 = lo - 2 * rlo * H
+            assert np.array_equal(Rb, R[i0:i0 + hi - lo])
+            assert np.allclose(Mb, M[i0:i0 + hi - lo], rtol=1e-12, atol=0)
+            assert np.array_equal(Zb, Zs[i0:i0 + hi - lo])
+
+
 def test_zero_series_normalises_to_zero_power():
     Ah, norm = O.normalise(O.spectrum(np.zeros(64)))
     assert norm == 0.0 and not np.any(Ah)
