@@ -344,6 +344,28 @@ fdas_status fdas_plan_get_info(fdas_plan p, fdas_plan_info *out);
 #define FDAS_NPHASES 9
 fdas_status fdas_profile_read(fdas_plan p, double *ms, int64_t *launches, int32_t reset);
 
+/* ------------------------------------------------------------------ no allocation
+ *
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. fdas_spectrum_noalloc
+ * computes what fdas_spectrum returns on a plan with the default (median)
+ * normalisation, without a plan: the un-normalised spectra A_k, k = 0..nsamp/2,
+ * as interleaved (re, im) float32 pairs [nseries][nsamp/2+1][2] into spec_dev
+ * (device, caller-owned), and, if norm_host is not NULL, each series' median
+ * normalisation (float64 [nseries], host). It calls no allocating routine: its
+ * FFT buffers, scales and median histograms live in a fixed device array of
+ * FDAS_NOALLOC_SCRATCH_BYTES per GPU, kept until the process ends, so
+ * 2 nseries (nsamp/2) 8 bytes plus about 8 KiB per series must fit in it
+ * (e.g. 8 series of 2^20 samples); larger requests return FDAS_E_INVAL.
+ * Calls on one GPU share that array: calls that overlap on one GPU (other
+ * streams or host threads) race; consecutive calls are independent.
+ * Errors: FDAS_E_INVAL (NULL or misaligned pointer, odd nsamp or below 8,
+ * nseries outside 1..65535, too large), FDAS_E_UNSUPPORTED (nsamp not a power of
+ * two), FDAS_E_DEVICE (a HIP call failed). */
+#define FDAS_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+fdas_status fdas_spectrum_noalloc(const float *series_dev, int64_t nsamp, int32_t nseries,
+                                  float *spec_dev, double *norm_host, void *stream);
+
 /* Description of a status code (static storage). */
 const char *fdas_status_string(fdas_status s);
 

@@ -28,7 +28,7 @@ EXPORTED = (
     "fdas_template_taps", "fdas_status_string", "fdas_last_error", "fdas_profile_read",
     "fdas_plan_get_info", "fdas_search_ragged", "fdas_tuning_export", "fdas_tuning_import",
     "fdas_refine_eval", "fdas_refine_grad", "fdas_refine", "fdas_refine_window", "fdas_dedisperse",
-    "fdas_sift",
+    "fdas_sift", "fdas_spectrum_noalloc",
 )
 PHASES = ("rfft", "normalise", "plane", "harmsum", "compact", "sigma", "copyout", "refine", "dedisperse")
 
@@ -143,6 +143,8 @@ def load(path: Optional[str] = None):
     lib.fdas_dedisperse.restype = c.c_int
     lib.fdas_sift.argtypes = [P, c.c_int64, c.c_double, c.c_int32, P, c.c_int64, c.POINTER(c.c_int64)]
     lib.fdas_sift.restype = c.c_int
+    lib.fdas_spectrum_noalloc.argtypes = [P, c.c_int64, c.c_int32, P, c.POINTER(c.c_double), P]
+    lib.fdas_spectrum_noalloc.restype = c.c_int
     _lib = lib
     return lib
 
@@ -396,6 +398,26 @@ class Plan:
         if st != FDAS_OK:
             self._raise(st, "fdas_spectrum")
         return torch.view_as_complex(out), np.array(norm[:], dtype=np.float64)
+
+
+def spectrum_noalloc(t, out=None, stream=None):
+    """(A, norm) as Plan.spectrum with the median normalisation, through the entry
+    point that allocates nothing (fixed per-GPU scratch). out: optional CUDA float32
+    [B][N/2+1][2] to write into (the caller's allocation)."""
+    import torch
+    lib = load()
+    t = _check_series(t)
+    B, N = t.shape
+    if out is None:
+        out = torch.empty((B, N // 2 + 1, 2), dtype=torch.float32, device=t.device)
+    elif out.shape != (B, N // 2 + 1, 2) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [B][N/2+1][2] tensor")
+    norm = (ctypes.c_double * B)()
+    st = lib.fdas_spectrum_noalloc(ctypes.c_void_p(t.data_ptr()), N, B, ctypes.c_void_p(out.data_ptr()), norm,
+                                   _stream_handle(stream))
+    if st != FDAS_OK:
+        raise FdasError(st, f"fdas_spectrum_noalloc: {lib.fdas_status_string(st).decode()}")
+    return torch.view_as_complex(out), np.array(norm[:], dtype=np.float64)
 
 
 def geometry(nsamp: int, tsamp: float, zmax: float, dz: float, opts: Optional[PlanOpts] = None):
