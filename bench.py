@@ -277,6 +277,60 @@ def write_traffic(res, workload, f_scale, w_scale, seg_len=None):
         json.dump(data, fh, indent=1, sort_keys=True)
 
 
+def launch_tails_summary(trace_csv: str, title: str, command: str, steps: int) -> str:
+    """Markdown summary of what grouped launches cost beyond their work, from a
+    rocprofv3 --kernel-trace CSV of eager searches.
+
+    Per kernel family, the launch with the most workgroups sets the time per
+    workgroup; every launch's excess over (its workgroups x that time) is its
+    tail (an under-filled machine at the start and end of a small launch). Gaps
+    are idle device time between consecutive kernels of the timed searches."""
+    import csv
+    rows = [r for r in csv.DictReader(open(trace_csv)) if r.get("Kind", "KERNEL_DISPATCH") == "KERNEL_DISPATCH"]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    fam = {}
+    for r in rows:
+        name = _kernel_key(r["Kernel_Name"])
+        if not name.startswith("fdas::"):
+            continue
+        wg = (int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))) * int(r["Grid_Size_Y"]) * \
+            int(r["Grid_Size_Z"])
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6   # ms
+        fam.setdefault(name, []).append((wg, dur, int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    out = [f"# Launch tails: {title}", "", "Command (repository root on the GPU box as $REPO):", "", "```", command,
+           "```", "",
+           "Per kernel family, the largest launch's time per workgroup is taken as the full-machine rate; a "
+           "launch's tail is its duration minus its workgroups at that rate. Gaps: idle device time between "
+           "consecutive kernels. Figures per search.", "",
+           "| kernel | launches per search | ms per search | tail ms per search | tail % of kernel |",
+           "|---|---|---|---|---|"]
+    total_ms = total_tail = 0.0
+    for name, ls in sorted(fam.items(), key=lambda kv: -sum(d for _, d, _, _ in kv[1])):
+        big = max(ls, key=lambda x: x[0])
+        rate = big[1] / max(1, big[0])
+        dur = sum(d for _, d, _, _ in ls)
+        tail = sum(max(0.0, d - w * rate) for w, d, _, _ in ls)
+        total_ms += dur
+        total_tail += tail
+        out.append(f"| `{name}` | {len(ls) / steps:.1f} | {dur / steps:.3f} | {tail / steps:.3f} | "
+                   f"{100 * tail / max(dur, 1e-12):.1f} |")
+    spans = sorted((a, b) for ls in fam.values() for _, _, a, b in ls)
+    busy = gaps = 0.0
+    cur_a, cur_b = spans[0]
+    for a_, b_ in spans[1:]:
+        if a_ > cur_b:
+            busy += (cur_b - cur_a) * 1e-6
+            gaps += (a_ - cur_b) * 1e-6
+            cur_a, cur_b = a_, b_
+        else:
+            cur_b = max(cur_b, b_)
+    busy += (cur_b - cur_a) * 1e-6
+    out += ["", f"Kernels {total_ms / steps:.3f} ms per search, of which tails {total_tail / steps:.3f} ms "
+                f"({100 * total_tail / total_ms:.1f} %); device busy {busy / steps:.3f} ms, gaps between kernels "
+                f"{gaps / steps:.3f} ms per search (gaps include the host work between searches)."]
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +354,8 @@ def main():
                     help="write a markdown summary of a rocprofv3 kernel-stats CSV and exit")
     ap.add_argument("--summary-title", default="",
                     help="workload description for --stats-summary (default: the config's workload name)")
+    ap.add_argument("--tails-summary", nargs=4, metavar=("TRACE_CSV", "OUT_MD", "COMMAND", "SEARCHES"),
+                    help="write the launch-tail summary of a rocprofv3 kernel trace and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND"),
                     help="summarise FETCH_SIZE/WRITE_SIZE runs into OUT_MD and profiles/traffic.json")
     ap.add_argument("--pmc-seg-len", type=int, default=2048,
@@ -310,6 +366,12 @@ def main():
         title = args.summary_title or _workload(args.config).name
         with open(out_md, "w") as fh:
             fh.write(stats_summary(csv_path, f"Kernel time summary: {title}", cmd))
+        return
+    if args.tails_summary:
+        csv_path, out_md, cmd, n = args.tails_summary
+        title = args.summary_title or _workload(args.config).name
+        with open(out_md, "w") as fh:
+            fh.write(launch_tails_summary(csv_path, title, cmd, int(n)))
         return
     if args.pmc_summary:
         fcsv, wcsv, out_md, cmd = args.pmc_summary

@@ -48,7 +48,7 @@ typedef enum {
     FDAS_E_NOMEM = -2,        /* device or host allocation failed */
     FDAS_E_DEVICE = -3,       /* a HIP call failed; sticky on the plan */
     FDAS_E_TRUNC = -4,        /* more candidates than the caller's capacity */
-    FDAS_E_UNSUPPORTED = -5   /* valid but not supported (e.g. N not a power of two) */
+    FDAS_E_UNSUPPORTED = -5   /* valid but not supported (e.g. N/2 with a prime factor above 5) */
 } fdas_status;
 
 /* FDAS_NORM_LOCAL (red-noise normalisation): bins 1..N/2-1 are cut into blocks
@@ -133,7 +133,10 @@ void fdas_plan_destroy(fdas_plan p);
  * maxima. Errors: FDAS_E_INVAL when nsamp is odd, nsamp > max_nsamp, the
  * searched band is empty, zmax is not a whole multiple of dz, numharm is not
  * a power of two <= 32, sigma <= 0 or not finite, tsamp <= 0;
- * FDAS_E_UNSUPPORTED when nsamp is not a power of two. NaN samples are not
+ * FDAS_E_UNSUPPORTED when nsamp / 2 is not a product of powers of 2, 3 and 5
+ * or exceeds 2^26 (a 2100.224 s file sampled at 250 us, 8400896 samples, is
+ * searched as its first 8398080 samples, nsamp / 2 = 2^7 3^8 5, or padded by
+ * the caller to 8437500). NaN samples are not
  * checked: they propagate into the powers. The caller keeps ownership of
  * all buffers; the plan keeps no caller pointer after return. */
 fdas_status fdas_search(fdas_plan p, const float *series_dev, int64_t nsamp, int32_t nseries,
@@ -360,8 +363,8 @@ fdas_status fdas_profile_read(fdas_plan p, double *ms, int64_t *launches, int32_
  * Calls on one GPU share that array: calls that overlap on one GPU (other
  * streams or host threads) race; consecutive calls are independent.
  * Errors: FDAS_E_INVAL (NULL or misaligned pointer, odd nsamp or below 8,
- * nseries outside 1..65535, too large), FDAS_E_UNSUPPORTED (nsamp not a power of
- * two), FDAS_E_DEVICE (a HIP call failed). */
+ * nseries outside 1..65535, too large), FDAS_E_UNSUPPORTED (nsamp / 2 not a
+ * product of powers of 2, 3 and 5), FDAS_E_DEVICE (a HIP call failed). */
 #define FDAS_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
 fdas_status fdas_spectrum_noalloc(const float *series_dev, int64_t nsamp, int32_t nseries,
                                   float *spec_dev, double *norm_host, void *stream);

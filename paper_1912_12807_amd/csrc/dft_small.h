@@ -1,4 +1,4 @@
-// Register-resident complex helpers and small DFTs (radix 2 to 32) for the
+// Register-resident complex helpers and small DFTs (radix 2 to 32, 3 and 5) for the
 // FFT kernels. DIR = -1 computes X_k = sum_n v_n exp(-2 pi i n k / R),
 // DIR = +1 the unnormalised inverse. Complex values are float2 (x = re, y = im).
 #pragma once
@@ -63,6 +63,43 @@ __device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 
     a2 = csub(t0, t2);
     a1 = cadd(t1, t3);
     a3 = csub(t1, t3);
+}
+
+// in-place 3-point DFT: with w = exp(DIR 2 pi i / 3) = -1/2 + DIR i sqrt(3)/2,
+// X1 = a0 - (a1 + a2)/2 + DIR i sqrt(3)/2 (a1 - a2), X2 the conjugate combination
+template <int DIR>
+__device__ __forceinline__ void dft3(float2 *v) {
+    constexpr float s = 0.86602540378443864676f * DIR;   // sin(2 pi / 3), signed
+    const float2 t = cadd(v[1], v[2]);
+    const float2 d = csub(v[1], v[2]);
+    const float2 m = make_float2(__fmaf_rn(-0.5f, t.x, v[0].x), __fmaf_rn(-0.5f, t.y, v[0].y));
+    const float2 r = make_float2(-s * d.y, s * d.x);       // DIR i sqrt(3)/2 (a1 - a2)
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+}
+
+// in-place 5-point DFT: with c_k = cos(2 pi k / 5), s_k = DIR sin(2 pi k / 5),
+// b1 = a1 + a4, b2 = a2 + a3, d1 = a1 - a4, d2 = a2 - a3:
+// X1,4 = a0 + c1 b1 + c2 b2 +- i (s1 d1 + s2 d2), X2,3 = a0 + c2 b1 + c1 b2 +- i (s2 d1 - s1 d2)
+template <int DIR>
+__device__ __forceinline__ void dft5(float2 *v) {
+    constexpr float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+    constexpr float s1 = 0.95105651629515357212f * DIR, s2 = 0.58778525229247312917f * DIR;
+    const float2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+    const float2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+    const float2 a0 = v[0];
+    const float2 p1 = make_float2(__fmaf_rn(c2, b2.x, __fmaf_rn(c1, b1.x, a0.x)),
+                                  __fmaf_rn(c2, b2.y, __fmaf_rn(c1, b1.y, a0.y)));
+    const float2 p2 = make_float2(__fmaf_rn(c1, b2.x, __fmaf_rn(c2, b1.x, a0.x)),
+                                  __fmaf_rn(c1, b2.y, __fmaf_rn(c2, b1.y, a0.y)));
+    const float2 q1 = make_float2(__fmaf_rn(s2, d2.x, __fmul_rn(s1, d1.x)), __fmaf_rn(s2, d2.y, __fmul_rn(s1, d1.y)));
+    const float2 q2 = make_float2(__fmaf_rn(-s1, d2.x, __fmul_rn(s2, d1.x)), __fmaf_rn(-s1, d2.y, __fmul_rn(s2, d1.y)));
+    v[0] = cadd(a0, cadd(b1, b2));
+    v[1] = make_float2(p1.x - q1.y, p1.y + q1.x);       // p1 + i q1
+    v[4] = make_float2(p1.x + q1.y, p1.y - q1.x);       // p1 - i q1
+    v[2] = make_float2(p2.x - q2.y, p2.y + q2.x);
+    v[3] = make_float2(p2.x + q2.y, p2.y - q2.x);
 }
 
 // in-place 8-point DFT of v[0..7] (natural order in and out)
@@ -155,6 +192,10 @@ template <int R, int DIR>
 __device__ __forceinline__ void dft_r(float2 *v) {
     if constexpr (R == 2) {
         dft2<DIR>(v[0], v[1]);
+    } else if constexpr (R == 3) {
+        dft3<DIR>(v);
+    } else if constexpr (R == 5) {
+        dft5<DIR>(v);
     } else if constexpr (R == 4) {
         dft4<DIR>(v[0], v[1], v[2], v[3]);
     } else if constexpr (R == 8) {
@@ -162,7 +203,7 @@ __device__ __forceinline__ void dft_r(float2 *v) {
     } else if constexpr (R == 16) {
         dft16<DIR>(v);
     } else {
-        static_assert(R == 32, "radix 2, 4, 8, 16 or 32");
+        static_assert(R == 32, "radix 2, 3, 4, 5, 8, 16 or 32");
         dft32<DIR>(v);
     }
 }

@@ -554,7 +554,8 @@ fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
     const int64_t sstride = (int64_t)g.NZ * pitch;
     RowBlocks rb;
     TRY(get_rows(p, g.NZ, cg.zgroups, cfg.bz, numharm, cfg.pair != 0, rb));
-    const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? pitch / 2 : pitch);
+    rb.ppitch = rb.pair ? pitch / 2 : pitch;
+    const int64_t psstride = (int64_t)rb.nblk * rb.ppitch;
     // K4 writes the block maxima whenever the buffer sized at plan creation
     // holds those of a chunk series. The exhaustive sums do not read them, but
     // every search then builds its plane with the same kernel instance, so that
@@ -904,7 +905,7 @@ fdas_status check_common(fdas_plan p, const void *dev, int64_t nsamp, int32_t ns
     if (nsamp > p->max_nsamp) return p->fail(FDAS_E_INVAL, "nsamp exceeds the plan's max_nsamp");
     fdas_status s = geometry(nsamp, tsamp, zmax, dz, p->opts.flo_hz, g);
     if (s != FDAS_OK) return p->fail(s, "invalid nsamp/tsamp/zmax/dz (odd nsamp, zmax not a multiple of dz, or empty band)");
-    if (!pow2(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp must be a power of two");
+    if (!fft_length_supported(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp / 2 must be a product of powers of 2, 3 and 5 (at most 2^26)");
     return FDAS_OK;
 }
 
@@ -1023,7 +1024,6 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
         return FDAS_E_INVAL;
     Geometry g;
     if (geometry(max_nsamp, 1e-3, zmax, dz, 0.0, g) != FDAS_OK) return FDAS_E_INVAL;
-    if (!pow2(max_nsamp)) return FDAS_E_UNSUPPORTED;
     const int mseg = half_width(g.Z * dz, o.K);
     if (!choose_L(mseg, o.seg_len)) return o.seg_len ? FDAS_E_INVAL : FDAS_E_UNSUPPORTED;
 
@@ -1149,7 +1149,7 @@ fdas_status fdas_search_ragged(fdas_plan p, const float *series_dev, const int64
         if (nsamp[i] > p->max_nsamp) return p->fail(FDAS_E_INVAL, "nsamp exceeds the plan's max_nsamp");
         fdas_status s = geometry(nsamp[i], tsamp[i], zmax[i], dz, p->opts.flo_hz, g);
         if (s != FDAS_OK) return p->fail(s, "invalid nsamp/tsamp/zmax/dz of a series");
-        if (!pow2(nsamp[i])) return p->fail(FDAS_E_UNSUPPORTED, "nsamp must be a power of two");
+        if (!fft_length_supported(nsamp[i])) return p->fail(FDAS_E_UNSUPPORTED, "nsamp / 2 must be a product of powers of 2, 3 and 5 (at most 2^26)");
         TRY(check_fits(p, g));
         const auto key = std::make_tuple(g.nsamp, g.rlo, g.Z);
         auto it = gid.find(key);
@@ -1406,7 +1406,7 @@ fdas_status fdas_refine(fdas_plan p, const float *series_dev, int64_t nsamp, int
     if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
     if (nsamp < 8 || (nsamp & 1) || nsamp > p->max_nsamp)
         return p->fail(FDAS_E_INVAL, "nsamp odd, below 8 or above the plan's max_nsamp");
-    if (!pow2(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp must be a power of two");
+    if (!fft_length_supported(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp / 2 must be a product of powers of 2, 3 and 5 (at most 2^26)");
     if (!(dz > 0) || !std::isfinite(dz) || iters < 0 || iters > 10000 || n < 0 || n > 0x7fffffffLL ||
         (n > 0 && (!pts_host || !power_host)))
         return p->fail(FDAS_E_INVAL, "bad dz, iters or point arrays");
@@ -1488,7 +1488,9 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
     RowBlocks rb;
     TRY(get_rows(p, g.NZ, 1, p->opts.harm_block ? p->opts.harm_block : default_block_rows(numharm), numharm,
                  maxima_per_bin(p->opts.harm_pair, numharm), rb));
-    const int64_t psstride = (int64_t)rb.nblk * (rb.pair ? g.NR / 2 : g.NR);
+    // maxima rows padded like the search's (a multiple of 32 halves)
+    rb.ppitch = rb.pair ? round_up(g.NR, 64) / 2 : round_up(g.NR, 64);
+    const int64_t psstride = (int64_t)rb.nblk * rb.ppitch;
     int64_t chunk = std::min<int64_t>(p->max_series, p->maxv_cap / (NS * mpitch));
     const bool bounded = !p->opts.harm_bound && bounded_table_bytes(rb.nblk, numharm) <= kBoundTableMax &&
                          psstride <= kMaxPyrSeriesStride && p->pyr_cap >= psstride;
@@ -1544,7 +1546,7 @@ fdas_status fdas_spectrum(fdas_plan p, const float *series_dev, int64_t nsamp, i
     if (nseries < 1 || nseries > p->max_series) return p->fail(FDAS_E_INVAL, "nseries out of range");
     if (nsamp < 8 || (nsamp & 1) || nsamp > p->max_nsamp)
         return p->fail(FDAS_E_INVAL, "nsamp odd, below 8 or above the plan's max_nsamp");
-    if (!pow2(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp must be a power of two");
+    if (!fft_length_supported(nsamp)) return p->fail(FDAS_E_UNSUPPORTED, "nsamp / 2 must be a product of powers of 2, 3 and 5 (at most 2^26)");
     Geometry g;
     g.nsamp = nsamp;
     g.half = nsamp / 2;
@@ -1612,7 +1614,7 @@ fdas_status fdas_tuning_import(fdas_plan p, const char *text) {
         int64_t n = 0;
         int Z = -1, nh = 0, L = 0, bz = 0, harm_pair = -1;
         std::string rest;
-        if (!(ls >> n >> Z >> nh >> L >> bz >> harm_pair) || (ls >> rest) || !pow2(n) || Z < 0 ||
+        if (!(ls >> n >> Z >> nh >> L >> bz >> harm_pair) || (ls >> rest) || n < 8 || (n & 1) || Z < 0 ||
             !valid_numharm(nh) || !pow2(L) || L < 512 || L > 4096 || bz < 1 || bz > 64 ||
             (harm_pair != 0 && harm_pair != 1))
             return p->fail(FDAS_E_INVAL, "malformed tuning line: " + line);

@@ -72,7 +72,9 @@ struct DevCand {
 };
 
 // ---------------------------------------------------------------- launchers
-// K1: real FFT of nseries series of n samples (n a power of two >= 8).
+// K1: real FFT of nseries series of n samples: n even, >= 8, with n/2 a product of
+// powers of 2, 3 and 5 (fft_length_supported).
+bool fft_length_supported(int64_t n);
 // x: [nseries][n] float32; w0, w1: scratch [nseries][n/2] complex; spec: [nseries][spitch]
 // complex receiving A_k for k = 0..n/2.
 // offs (device, optional): series b starts at x + 2 offs[b] floats (ragged batches);
@@ -119,6 +121,7 @@ struct RowBlocks {
     int nblk = 0;
     int frange_nh = 0;
     bool pair = false;                // maxima per bin (both parities) instead of per column
+    int64_t ppitch = 0;               // halves per row block of the maxima (a multiple of 32)
 };
 // Host construction of the row-block partition for NZ rows, G z groups and
 // blocks of at most bz rows (as even as possible inside each group).

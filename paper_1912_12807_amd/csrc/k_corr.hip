@@ -389,7 +389,8 @@ hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *sc
     if ((int64_t)2 * g.NZ * g.L * 8 > 0x7fffffffLL || (int64_t)2 * g.Lv * 4 > 0x7fffffffLL)
         return hipErrorInvalidValue;
     if (nseries < 1 || g.nseg < 1 || g.Lv < 1 || (g.zgroups & (g.zgroups - 1)) || g.zgroups > 8 ||
-        g.zgroups < 1 || (pitch & 1) || (pyr && (!rb.lo || !rb.of_row || rb.nblk < 1)))
+        g.zgroups < 1 || (pitch & 1) ||
+        (pyr && (!rb.lo || !rb.of_row || rb.nblk < 1 || rb.ppitch != (rb.pair ? pitch / 2 : pitch))))
         return hipErrorInvalidValue;
     const int64_t units = (int64_t)nseries * g.nseg;
     const int per = 8 / g.zgroups;

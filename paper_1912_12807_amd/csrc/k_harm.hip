@@ -189,6 +189,7 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
 // Maxima are gathered as halves (half the bytes and cache lines).
 // The kernel is bound by the latency of these gathers, so occupancy matters
 // more than sharing the block bookkeeping between many series per lane.
+
 template <int NH>
 struct BoundCfg {
     // series per lane: the wave-uniform block bookkeeping is shared by SB series
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
                                                     const float *__restrict__ thr,
                                                     float *__restrict__ maxv, int16_t *__restrict__ zarg,
                                                     int64_t mpitch, int64_t tiles_per_series,
-                                                    int64_t total_tiles, int pair, int nseries) {
+                                                    int64_t total_tiles, int pair, int64_t ppitch, int nseries) {
     constexpr int NS = Stages<NH>::NS;
     constexpr int SB = BoundCfg<NH>::SB;
 
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
         const int bm = b0 + m < nseries ? b0 + m : nseries - 1;   // spare lanes re-read the last series
         yb[m] = pyr + (int64_t)bm * psstride;
     }
-    const uint32_t rowb = (uint32_t)(pair ? pitch / 2 : pitch) * (uint32_t)sizeof(bmax_t);   // bytes per row
+    const uint32_t rowb = (uint32_t)ppitch * (uint32_t)sizeof(bmax_t);   // bytes per row block
     float th[NS];
     bool valid[NS];
 #pragma unroll
@@ -453,7 +454,8 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
 __global__ __launch_bounds__(256) void k_block_max(const float *__restrict__ plane, int64_t pitch,
                                                    int64_t sstride, int64_t NR,
                                                    const int32_t *__restrict__ blk_lo, int nblk,
-                                                   bmax_t *__restrict__ pyr, int64_t psstride, int pair) {
+                                                   bmax_t *__restrict__ pyr, int64_t psstride, int pair,
+                                                   int64_t ppitch) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int k = blockIdx.y, b = blockIdx.z;
     const int64_t ncol = pair ? NR / 2 : NR;
@@ -464,19 +466,19 @@ __global__ __launch_bounds__(256) void k_block_max(const float *__restrict__ pla
         const float *q = src + (int64_t)r * pitch;
         mx = fmaxf(mx, pair ? fmaxf(q[0], q[1]) : q[0]);
     }
-    pyr[(int64_t)b * psstride + (int64_t)k * (pair ? pitch / 2 : pitch) + i] = bound_half(mx);
+    pyr[(int64_t)b * psstride + (int64_t)k * ppitch + i] = bound_half(mx);
 }
 
 hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
                             const RowBlocks &rb, int nseries, bmax_t *pyr, int64_t pyr_series_stride,
                             hipStream_t st) {
-    if (nseries < 1 || nseries > 65535 || rb.nblk < 1 || rb.nblk > 65535 || !rb.lo || (pitch & 1) ||
-        (NR & 1))
-        return hipErrorInvalidValue;
     const int64_t ncol = rb.pair ? NR / 2 : NR;
+    if (nseries < 1 || nseries > 65535 || rb.nblk < 1 || rb.nblk > 65535 || !rb.lo || (pitch & 1) ||
+        (NR & 1) || rb.ppitch < ncol || (rb.ppitch & 31) || pyr_series_stride < rb.nblk * rb.ppitch)
+        return hipErrorInvalidValue;
     dim3 grid((unsigned)((ncol + 255) / 256), (unsigned)rb.nblk, (unsigned)nseries);
     hipLaunchKernelGGL(k_block_max, grid, dim3(256), 0, st, plane, pitch, series_stride, NR, rb.lo,
-                       rb.nblk, pyr, pyr_series_stride, rb.pair ? 1 : 0);
+                       rb.nblk, pyr, pyr_series_stride, rb.pair ? 1 : 0, rb.ppitch);
     return hipGetLastError();
 }
 
@@ -672,7 +674,7 @@ static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, 
     const int64_t nwg = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL(k_harm_bound<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
                        pyr, psstride, rb.lo, rb.frange, rb.nblk, NR, rlo, Z, thr, maxv, zarg, mpitch, tps,
-                       total, rb.pair ? 1 : 0, nseries);
+                       total, rb.pair ? 1 : 0, rb.ppitch, nseries);
 }
 
 hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
@@ -684,7 +686,8 @@ hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t ser
     if (nseries < 1 || mpitch < NR || (mpitch & 15) || (mpitch + 255) / 256 * nseries > 0x7ffffff0LL ||
         !pyr || !rb.lo || !rb.frange || rb.nblk < 1 || rb.frange_nh != numharm ||
         bounded_table_bytes(rb.nblk, numharm) > kBoundTableMax || pyr_series_stride > kMaxPyrSeriesStride ||
-        !zarg || Z > 32767)
+        !zarg || Z > 32767 || (rb.ppitch & 31) || rb.ppitch < (rb.pair ? NR / 2 : NR) ||
+        pyr_series_stride < rb.nblk * rb.ppitch)
         return hipErrorInvalidValue;
 #define FDAS_BOUND(NHV) launch_bound_nh<NHV>(plane, pitch, series_stride, pyr, pyr_series_stride, rb, NR, rlo, Z, nseries, thr_dev, maxv, zarg, mpitch, st)
     switch (numharm) {

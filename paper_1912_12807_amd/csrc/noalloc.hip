@@ -53,7 +53,7 @@ extern "C" fdas_status fdas_spectrum_noalloc(const float *series_dev, int64_t ns
     if (!series_dev || ((uintptr_t)series_dev & 7) || !spec_dev || ((uintptr_t)spec_dev & 7))
         return FDAS_E_INVAL;
     if (nseries < 1 || nseries > 65535 || nsamp < 8 || (nsamp & 1)) return FDAS_E_INVAL;
-    if (nsamp & (nsamp - 1)) return FDAS_E_UNSUPPORTED;
+    if (!fft_length_supported(nsamp)) return FDAS_E_UNSUPPORTED;
     const int64_t half = nsamp / 2;
     // scratch layout: FFT buffers w0, w1 [nseries][half], scales, norms, median scratch
     const size_t fft_bytes = align256((size_t)nseries * (size_t)half * sizeof(float2));

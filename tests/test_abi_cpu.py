@@ -116,7 +116,8 @@ def test_plan_create_rejects_bad_arguments_before_touching_a_device(F):
     assert lib.fdas_plan_create(ctypes.byref(h), 1 << 12, 1, 10.0, 2.0, 1, ctypes.byref(o)) == F.FDAS_E_INVAL
     o = F.default_opts(fail_alloc=-1)
     assert lib.fdas_plan_create(ctypes.byref(h), 1 << 12, 1, 10.0, 2.0, 1, ctypes.byref(o)) == F.FDAS_E_INVAL
-    assert lib.fdas_plan_create(ctypes.byref(h), 3000, 1, 10.0, 2.0, 1, None) == F.FDAS_E_UNSUPPORTED
+    # a drift range whose templates outgrow the largest correlation segment
+    assert lib.fdas_plan_create(ctypes.byref(h), 1 << 12, 1, 8000.0, 2.0, 1, None) == F.FDAS_E_UNSUPPORTED
     assert not h.value
 
 

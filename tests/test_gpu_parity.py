@@ -27,9 +27,16 @@ def _noise(B, N, seed):
 
 # ----------------------------------------------------------------------------- spectrum
 
-@pytest.mark.parametrize("N", [8, 64, 1 << 12, 1 << 17])
+SPECTRUM_LENGTHS = [
+    8, 64, 1 << 12, 1 << 14, 1 << 15, 1 << 17, 1 << 23,       # one workgroup up to 2^14, four-step above
+    12, 30, 4374, 12000,                                      # N/2 = 6, 15, 3^7, 2^4 3 5^3: in one workgroup
+    31250, 153600, 6291456,                                   # N/2 = 5^6, 2^10 3 5^2, 3 2^20: four-step
+]
+
+
+@pytest.mark.parametrize("N", SPECTRUM_LENGTHS)
 def test_spectrum_and_median_norm(fdas_gpu, N):
-    B = 3
+    B = 3 if N < (1 << 22) else 2
     x = _noise(B, N, N)
     x[1] *= 5.0
     plan = fdas_gpu.Plan(N, B, 0.0, 2.0, 1, flo_hz=0.0)
@@ -170,6 +177,29 @@ def test_search_matches_oracle(fdas_gpu, case):
     oracles = {b: OracleSeries(x[b], ts, zmax, dz, nh, method="fft") for b in range(B)}
     common, banded = assert_candidates_match(g, oracles, sigma)
     assert common >= 1
+
+
+SMOOTH_CASES = [
+    # (B, N, tsamp, zmax, dz, numharm, sigma): N/2 = 2^4 3 5^3 (one workgroup FFT) and
+    # 2^10 3 5^2 (four-step FFT)
+    (2, 12000, 1e-3, 20.0, 2.0, 4, 5.0),
+    (2, 153600, 2e-4, 50.0, 2.0, 8, 6.0),
+]
+
+
+@pytest.mark.parametrize("case", SMOOTH_CASES, ids=lambda c: f"B{c[0]}-N{c[1]}-z{c[3]}-h{c[5]}")
+def test_search_5smooth_lengths_match_oracle(fdas_gpu, case):
+    B, N, ts, zmax, dz, nh, sigma = case
+    wl = synth.small_batch(B, N, ts, zmax, dz, nh, sigma=sigma, config=83, signals=B, amp_range=(0.3, 1.0))
+    x = synth.generate(wl)
+    plan = fdas_gpu.Plan(N, B, zmax, dz, nh)
+    g = plan.search(_cuda(x), ts, sigma=sigma, cap=1 << 18)
+    oracles = {b: OracleSeries(x[b], ts, zmax, dz, nh, method="fft") for b in range(B)}
+    common, _ = assert_candidates_match(g, oracles, sigma)
+    assert common >= 1
+    P = plan.plane(_cuda(x), ts).cpu().numpy()
+    for b in range(B):
+        assert_plane_close(P[b], oracles[b].plane)
 
 
 def test_search_chunked_workspace_matches_unchunked(fdas_gpu):

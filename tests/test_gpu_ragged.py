@@ -72,6 +72,25 @@ def test_ragged_matches_oracle_per_series(fdas_gpu, ragged):
     assert np.allclose(g["fdot_hz_s"], g["z_fund"] / T[g["series"]] ** 2, rtol=1e-15)
 
 
+# lengths whose halves are products of powers of 2, 3 and 5 (4374: 3^7, in one
+# workgroup; 15360, 12000 and 9720 in one workgroup or four-step)
+RAGGED_SMOOTH = [(12000, 1e-3, 20.0), (15360, 1e-3, 10.0), (12000, 1e-3, 0.0), (9720, 2e-3, 20.0),
+                 (4374, 1e-3, 10.0), (40000, 5e-4, 20.0)]
+
+
+def test_ragged_5smooth_lengths_match_oracle(fdas_gpu):
+    n, t, z = zip(*RAGGED_SMOOTH)
+    wl = synth.small_ragged(n, t, z, DZ, NH, SIGMA, config=84, signals=4, amp_range=(0.5, 1.5))
+    buf = synth.generate_ragged(wl)
+    offs = wl.offsets()
+    plan = _plan(fdas_gpu, wl, graph=1)
+    d = _cuda(buf)
+    g = plan.search_ragged(d, offs, wl.nsamp, wl.tsamp, wl.zmax, sigma=wl.sigma, cap=1 << 18)
+    assert _check_vs_oracle(g, wl, buf, offs) >= 10
+    again = plan.search_ragged(d, offs, wl.nsamp, wl.tsamp, wl.zmax, sigma=wl.sigma, cap=1 << 18)   # replay
+    assert np.array_equal(g, again)
+
+
 def test_ragged_equals_per_series_calls(fdas_gpu, ragged):
     wl, buf, offs = ragged
     plan = _plan(fdas_gpu, wl)
@@ -189,7 +208,7 @@ def test_ragged_invalid_arguments(fdas_gpu, ragged):
     expect(F.FDAS_E_INVAL, z_=[11.0] + z[1:])                  # zmax not a multiple of dz
     expect(F.FDAS_E_INVAL, t_=[0.0] + t[1:])
     expect(F.FDAS_E_INVAL, numharm=8)                          # above the plan's numharm
-    expect(F.FDAS_E_UNSUPPORTED, n_=[n[0] - 16] + n[1:])       # not a power of two
+    expect(F.FDAS_E_UNSUPPORTED, n_=[n[0] - 16] + n[1:])       # N/2 = 2040 has the prime factor 17
     with pytest.raises(ValueError):
         plan.search_ragged(d, offs + 8, n, t, z)               # last series past the buffer
     big = F.Plan(1 << 12, 2, 10.0, 2.0, 4)

@@ -51,7 +51,8 @@ def test_noalloc_spectrum_on_a_side_stream_and_limits(fdas_gpu):
     # beyond the fixed scratch: 2 buffers of nseries * N/2 complex values > 64 MiB
     big = lib.fdas_spectrum_noalloc(P(x.data_ptr()), 1 << 24, 1, P(out.data_ptr()), None, None)
     assert big == fdas_gpu.FDAS_E_INVAL
-    assert lib.fdas_spectrum_noalloc(P(x.data_ptr()), 3 * 4096, 1, P(out.data_ptr()), None, None) == \
+    # nsamp / 2 = 7 * 1024 has a prime factor above 5
+    assert lib.fdas_spectrum_noalloc(P(x.data_ptr()), 14 * 1024, 1, P(out.data_ptr()), None, None) == \
         fdas_gpu.FDAS_E_UNSUPPORTED
     assert lib.fdas_spectrum_noalloc(None, N, B, P(out.data_ptr()), None, None) == fdas_gpu.FDAS_E_INVAL
     assert lib.fdas_spectrum_noalloc(P(x.data_ptr()), N, 0, P(out.data_ptr()), None, None) == fdas_gpu.FDAS_E_INVAL
