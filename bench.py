@@ -339,6 +339,8 @@ def main():
     ap.add_argument("--config", type=int, default=3, choices=(1, 2, 3, 4, 5, 6, 7))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FAST-batch figures of the default run")
+    ap.add_argument("--eager-only", action="store_true",
+                    help="config 4: only warmup + steps eager grouped searches (for kernel traces)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", type=int, default=0, choices=(0, 1),
                     help="time candidate launch parameters on the first search (during warmup)")
@@ -624,6 +626,19 @@ def bench_ragged(args):
             c = call(plan)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, c
+
+    if args.eager_only:
+        # only warmup + steps eager grouped searches with the given launch parameters
+        # (for kernel traces: nothing else runs on the device)
+        plan = fdas.Plan(nmax, wl.nseries, zmax, wl.dz, wl.numharm)
+        if args.tuning:
+            plan.load_tuning(args.tuning.replace(";", "\n"))
+        for _ in range(args.warmup):
+            call(plan)
+        sec, cands = timed(plan, args.steps)
+        print(json.dumps({"workload": wl.name, "eager_ms_per_search": 1e3 * sec, "searches": args.warmup + args.steps,
+                          "cells_per_step": cells, "candidates": int(len(cands))}), flush=True)
+        return
 
     plan = fdas.Plan(nmax, wl.nseries, zmax, wl.dz, wl.numharm, autotune=1, graph=1)
     if args.tuning:
