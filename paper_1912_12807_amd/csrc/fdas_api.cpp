@@ -216,6 +216,11 @@ struct fdas_plan_s {
     unsigned long long *d_csum = nullptr;   // per-channel sums and rounded means
     float *d_cpad = nullptr;
     int32_t cpad_cap = 0;
+    // work lists of the merged bounded harmonic sums of a batch (and their staging)
+    HarmItem *d_hitems = nullptr, *h_hitems = nullptr;
+    int64_t hitems_cap = 0, h_hitems_cap = 0;
+    int64_t *d_hstarts = nullptr, *h_hstarts = nullptr;
+    int64_t hstarts_cap = 0, h_hstarts_cap = 0;
     // refinement points
     fdas_refine_point *d_rpts = nullptr, *h_rpts = nullptr;
     float *d_rpow = nullptr, *h_rpow = nullptr;
@@ -544,58 +549,106 @@ fdas_status run_spectrum(fdas_plan p, const float *x, const int64_t *offs, int64
     return FDAS_OK;
 }
 
-// K4 [+ K5 + K6 + significance] for the nb series whose spectra are in batch slots
-// vbase..., in chunks that the workspace holds. timing_only stops after K5
-// (autotuner).
-fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const LaunchCfg &cfg,
-                       int numharm, int nb, int vbase, bool timing_only, hipStream_t st) {
-    const CorrGeom cg = corr_geom(bk, g);
-    const int64_t pitch = round_up(g.NR, 64);
-    const int64_t sstride = (int64_t)g.NZ * pitch;
+// One K4/K5/K6 unit of a search: series b0 ... b0 + n - 1 of a group (batch
+// slots vbase + b0 ...), with its regions of the plane, block-maxima and
+// stage-maxima buffers.
+struct WorkItem {
+    const Geometry *g = nullptr;
+    const Bank *bk = nullptr;
+    CorrGeom cg{};
     RowBlocks rb;
-    TRY(get_rows(p, g.NZ, cg.zgroups, cfg.bz, numharm, cfg.pair != 0, rb));
-    rb.ppitch = rb.pair ? pitch / 2 : pitch;
-    const int64_t psstride = (int64_t)rb.nblk * rb.ppitch;
+    int vbase = 0, b0 = 0, n = 0;
+    int64_t pitch = 0, sstride = 0, psstride = 0, mpitch = 0;
+    bool with_pyr = false, bounded = false;
+    int64_t plane_off = 0, pyr_off = 0, maxv_off = 0;   // elements into d_plane, d_pyr, d_maxv and d_zarg
+};
+
+// Layout of a group's series in the workspace (it, without series range or
+// offsets) and *chunk, the most of them the workspace holds at once.
+fdas_status group_item(fdas_plan p, const Geometry &g, const Bank &bk, const LaunchCfg &cfg, int numharm,
+                       int vbase, WorkItem &it, int64_t *chunk) {
+    it.g = &g;
+    it.bk = &bk;
+    it.cg = corr_geom(bk, g);
+    it.vbase = vbase;
+    it.pitch = round_up(g.NR, 64);
+    it.sstride = (int64_t)g.NZ * it.pitch;
+    TRY(get_rows(p, g.NZ, it.cg.zgroups, cfg.bz, numharm, cfg.pair != 0, it.rb));
+    it.rb.ppitch = it.rb.pair ? it.pitch / 2 : it.pitch;
+    it.psstride = (int64_t)it.rb.nblk * it.rb.ppitch;
     // K4 writes the block maxima whenever the buffer sized at plan creation
     // holds those of a chunk series. The exhaustive sums do not read them, but
     // every search then builds its plane with the same kernel instance, so that
     // bounded and exhaustive searches return bit-identical records. When they
     // do not fit, the plane is built without maxima (the chunk is then not
     // limited by their buffer) and every cell is summed.
-    const bool with_pyr = psstride <= kMaxPyrSeriesStride && psstride <= p->pyr_cap;
-    const bool bounded = with_pyr && !p->opts.harm_bound && bounded_table_bytes(rb.nblk, numharm) <= kBoundTableMax;
+    it.with_pyr = it.psstride <= kMaxPyrSeriesStride && it.psstride <= p->pyr_cap;
+    it.bounded = it.with_pyr && !p->opts.harm_bound && bounded_table_bytes(it.rb.nblk, numharm) <= kBoundTableMax;
+    it.mpitch = round_up(g.NR, 16);
     const int NS = nstages_of(numharm);
-    const int64_t mpitch = round_up(g.NR, 16);
-    int64_t chunk = std::min<int64_t>(p->plane_cap / sstride, p->maxv_cap / (NS * mpitch));
-    if (with_pyr) chunk = std::min<int64_t>(chunk, p->pyr_cap / psstride);
-    if (chunk < 1) return p->fail(FDAS_E_INVAL, "one series' plane exceeds the workspace");
-    p->last_harm_blocks = bounded ? rb.nblk : 0;
-    p->last_harm_pair = rb.pair ? 1 : 0;
+    int64_t c = std::min<int64_t>(p->plane_cap / it.sstride, p->maxv_cap / (NS * it.mpitch));
+    if (it.with_pyr) c = std::min<int64_t>(c, p->pyr_cap / it.psstride);
+    if (c < 1) return p->fail(FDAS_E_INVAL, "one series' plane exceeds the workspace");
+    *chunk = c;
+    p->last_harm_blocks = it.bounded ? it.rb.nblk : 0;
+    p->last_harm_pair = it.rb.pair ? 1 : 0;
     p->last_L = bk.L;
     p->last_mseg = bk.mseg;
     p->last_NZ = g.NZ;
+    return FDAS_OK;
+}
+
+fdas_status launch_item_k4(fdas_plan p, const WorkItem &it, hipStream_t st) {
+    const int64_t v = it.vbase + it.b0;
+    hipEvent_t e = p->begin(st);
+    HIPTRY(p, launch_corr_power(p->d_spec + v * p->spitch, p->spitch, p->d_scale + v, it.bk->d, it.cg, it.n,
+                                p->d_plane + it.plane_off, it.pitch, it.sstride,
+                                it.with_pyr ? p->d_pyr + it.pyr_off : nullptr, it.psstride, it.rb, st));
+    p->end(2, e, st);
+    return FDAS_OK;
+}
+
+// K5 of one item in a launch of its own.
+fdas_status launch_item_k5(fdas_plan p, const WorkItem &it, int numharm, hipStream_t st) {
+    const Geometry &g = *it.g;
+    hipEvent_t e = p->begin(st);
+    if (it.bounded) {
+        HIPTRY(p, launch_harmsum_bounded(p->d_plane + it.plane_off, it.pitch, it.sstride, p->d_pyr + it.pyr_off,
+                                         it.psstride, it.rb, g.NR, g.rlo, g.Z, numharm, it.n, p->d_thr,
+                                         p->d_maxv + it.maxv_off, p->d_zarg + it.maxv_off, it.mpitch, st));
+    } else {
+        const int order = p->opts.harm_order ? p->opts.harm_order : 1;
+        HIPTRY(p, launch_harmsum(p->d_plane + it.plane_off, it.pitch, it.sstride, g.NR, g.rlo, g.Z, numharm, it.n,
+                                 p->d_maxv + it.maxv_off, p->d_zarg + it.maxv_off, it.mpitch, order, st));
+    }
+    p->end(3, e, st);
+    return FDAS_OK;
+}
+
+fdas_status launch_item_k6(fdas_plan p, const WorkItem &it, int numharm, hipStream_t st) {
+    const int NS = nstages_of(numharm);
+    hipEvent_t e = p->begin(st);
+    HIPTRY(p, launch_compact(p->d_maxv + it.maxv_off, p->d_zarg + it.maxv_off, (int64_t)it.n * NS * it.mpitch,
+                             it.mpitch, NS, it.vbase + it.b0, p->d_thr, p->d_counts, p->d_offsets, p->d_state,
+                             p->d_rec, p->rec_cap, st));
+    p->end(4, e, st);
+    return FDAS_OK;
+}
+
+// K4 + K5 [+ K6] for the nb series of one group whose spectra are in batch
+// slots vbase..., in chunks that the workspace holds. timing_only stops after
+// K5 (autotuner).
+fdas_status run_chunks(fdas_plan p, const Geometry &g, const Bank &bk, const LaunchCfg &cfg,
+                       int numharm, int nb, int vbase, bool timing_only, hipStream_t st) {
+    WorkItem it;
+    int64_t chunk = 0;
+    TRY(group_item(p, g, bk, cfg, numharm, vbase, it, &chunk));
     for (int b0 = 0; b0 < nb; b0 += (int)chunk) {
-        const int n = (int)std::min<int64_t>(chunk, nb - b0);
-        hipEvent_t e = p->begin(st);
-        HIPTRY(p, launch_corr_power(p->d_spec + (int64_t)(vbase + b0) * p->spitch, p->spitch,
-                                    p->d_scale + vbase + b0, bk.d, cg, n, p->d_plane, pitch, sstride,
-                                    with_pyr ? p->d_pyr : nullptr, psstride, rb, st));
-        p->end(2, e, st);
-        e = p->begin(st);
-        if (bounded) {
-            HIPTRY(p, launch_harmsum_bounded(p->d_plane, pitch, sstride, p->d_pyr, psstride, rb, g.NR, g.rlo,
-                                             g.Z, numharm, n, p->d_thr, p->d_maxv, p->d_zarg, mpitch, st));
-        } else {
-            const int order = p->opts.harm_order ? p->opts.harm_order : 1;
-            HIPTRY(p, launch_harmsum(p->d_plane, pitch, sstride, g.NR, g.rlo, g.Z, numharm, n, p->d_maxv,
-                                     p->d_zarg, mpitch, order, st));
-        }
-        p->end(3, e, st);
-        if (timing_only) continue;
-        e = p->begin(st);
-        HIPTRY(p, launch_compact(p->d_maxv, p->d_zarg, (int64_t)n * NS * mpitch, mpitch, NS, vbase + b0, p->d_thr,
-                                 p->d_counts, p->d_offsets, p->d_state, p->d_rec, p->rec_cap, st));
-        p->end(4, e, st);
+        it.b0 = b0;
+        it.n = (int)std::min<int64_t>(chunk, nb - b0);
+        TRY(launch_item_k4(p, it, st));
+        TRY(launch_item_k5(p, it, numharm, st));
+        if (!timing_only) TRY(launch_item_k6(p, it, numharm, st));
     }
     return FDAS_OK;
 }
@@ -804,10 +857,121 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
     return total > cap ? FDAS_E_TRUNC : FDAS_OK;
 }
 
-// Enqueue every group of a batch on st. Groups of one length are adjacent in
-// the batch, so each length needs one K1 and one K2 launch.
-fdas_status enqueue_groups(fdas_plan p, const float *x, bool ragged, const Batch &B, double dz, int numharm,
-                           hipStream_t st) {
+// The work of a batch in waves. The items of a wave hold their own regions
+// of the workspace together: their K4 launches run first, then one bounded
+// K5 launch over the wave's bounded items (a work list), then their K6
+// launches. A ragged batch of many small groups thus ends one partly idle K5
+// tail per wave instead of one per group. A group of one search is split into
+// chunks of the series the workspace holds, one wave each.
+struct Wave {
+    std::vector<WorkItem> items;
+    int64_t plane = 0, pyr = 0, maxv = 0;   // elements of each buffer in use
+    int list0 = 0, nlist = 0;               // work-list entries list0 ... (used when nlist > 1)
+    int starts0 = 0;                        // its run starts (nlist + 1 entries)
+    int64_t runs = 0;                       // tiles per XCD of the work-list launch
+};
+
+struct WavePlan {
+    std::vector<Wave> waves;
+    std::vector<HarmItem> list;
+    std::vector<int64_t> starts;
+};
+
+// Items in batch order, each placed in the first wave with room in all three
+// buffers. The records of a search of one group stay in series order: every
+// full chunk fills one buffer too far to take another series, so each wave
+// holds one chunk and the chunks run in order.
+fdas_status plan_waves(fdas_plan p, const Batch &B, double dz, int numharm, WavePlan &W) {
+    W = WavePlan();
+    const int NS = nstages_of(numharm);
+    for (const Group &G : B.groups) {
+        const Bank *bk = nullptr;
+        TRY(get_bank(p, G.zmax, dz, G.cfg.L, &bk));
+        WorkItem it;
+        int64_t chunk = 0;
+        TRY(group_item(p, G.g, *bk, G.cfg, numharm, G.vbase, it, &chunk));
+        for (int b0 = 0; b0 < G.nb; b0 += (int)chunk) {
+            it.b0 = b0;
+            it.n = (int)std::min<int64_t>(chunk, G.nb - b0);
+            const int64_t pl = it.n * it.sstride, py = it.with_pyr ? it.n * it.psstride : 0;
+            const int64_t mv = (int64_t)it.n * NS * it.mpitch;
+            size_t w = 0;
+            while (w < W.waves.size() && (W.waves[w].plane + pl > p->plane_cap || W.waves[w].pyr + py > p->pyr_cap ||
+                                          W.waves[w].maxv + mv > p->maxv_cap))
+                ++w;
+            if (w == W.waves.size()) W.waves.emplace_back();
+            Wave &X = W.waves[w];
+            it.plane_off = X.plane;
+            it.pyr_off = X.pyr;
+            it.maxv_off = X.maxv;
+            X.plane += pl;
+            X.pyr += py;
+            X.maxv += mv;
+            X.items.push_back(it);
+        }
+    }
+    // work lists: a wave's bounded items, those with the most drift blocks
+    // (the costliest tiles) first
+    for (Wave &X : W.waves) {
+        std::vector<const WorkItem *> bi;
+        for (const WorkItem &it : X.items)
+            if (it.bounded) bi.push_back(&it);
+        X.nlist = (int)bi.size();
+        if (X.nlist < 2) continue;
+        std::stable_sort(bi.begin(), bi.end(),
+                         [](const WorkItem *a, const WorkItem *b) { return a->rb.nblk > b->rb.nblk; });
+        X.list0 = (int)W.list.size();
+        X.starts0 = (int)W.starts.size();
+        for (const WorkItem *it : bi) {
+            if (it->rb.frange_nh != numharm) return p->fail(FDAS_E_DEVICE, "internal error: row table of another numharm");
+            HarmItem h{};
+            h.plane = p->d_plane + it->plane_off;
+            h.pitch = it->pitch;
+            h.sstride = it->sstride;
+            h.pyr = p->d_pyr + it->pyr_off;
+            h.psstride = it->psstride;
+            h.ppitch = it->rb.ppitch;
+            h.blk_lo = it->rb.lo;
+            h.frange = it->rb.frange;
+            h.maxv = p->d_maxv + it->maxv_off;
+            h.zarg = p->d_zarg + it->maxv_off;
+            h.mpitch = it->mpitch;
+            h.NR = it->g->NR;
+            h.rlo = it->g->rlo;
+            h.nblk = it->rb.nblk;
+            h.Z = it->g->Z;
+            h.pair = it->rb.pair ? 1 : 0;
+            h.nseries = it->n;
+            W.list.push_back(h);
+        }
+        W.starts.resize(W.starts.size() + X.nlist + 1);
+        X.runs = harm_items_layout(W.list.data() + X.list0, X.nlist, numharm, W.starts.data() + X.starts0);
+        if (X.runs < 1) return p->fail(FDAS_E_DEVICE, "internal error: invalid harmonic-sum work list");
+    }
+    return FDAS_OK;
+}
+
+// Copy the work lists to the device on st (grown first if needed, so before
+// any capture).
+fdas_status upload_lists(fdas_plan p, const WavePlan &W, hipStream_t st) {
+    const int64_t ni = (int64_t)W.list.size(), ns = (int64_t)W.starts.size();
+    if (!ni) return FDAS_OK;
+    if (ni > p->hitems_cap) TRY(grow(p, &p->d_hitems, &p->hitems_cap, ni, "harmonic-sum work lists"));
+    if (ni > p->h_hitems_cap) TRY(grow(p, &p->h_hitems, &p->h_hitems_cap, ni, "harmonic-sum work lists", true));
+    if (ns > p->hstarts_cap) TRY(grow(p, &p->d_hstarts, &p->hstarts_cap, ns, "harmonic-sum work lists"));
+    if (ns > p->h_hstarts_cap) TRY(grow(p, &p->h_hstarts, &p->h_hstarts_cap, ns, "harmonic-sum work lists", true));
+    std::memcpy(p->h_hitems, W.list.data(), (size_t)ni * sizeof(HarmItem));
+    std::memcpy(p->h_hstarts, W.starts.data(), (size_t)ns * sizeof(int64_t));
+    HIPTRY(p, hipMemcpyAsync(p->d_hitems, p->h_hitems, (size_t)ni * sizeof(HarmItem), hipMemcpyHostToDevice, st));
+    HIPTRY(p, hipMemcpyAsync(p->d_hstarts, p->h_hstarts, (size_t)ns * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    return FDAS_OK;
+}
+
+// Enqueue every group of a batch on st: the spectra of each length (groups of
+// one length are adjacent in the batch: one K1 and one K2 launch per length),
+// then the waves.
+fdas_status enqueue_groups(fdas_plan p, const float *x, bool ragged, const Batch &B, const WavePlan &W,
+                           int numharm, hipStream_t st) {
     HIPTRY(p, launch_zero_state(p->d_state, st));
     for (size_t i = 0; i < B.groups.size();) {
         size_t j = i;
@@ -815,12 +979,19 @@ fdas_status enqueue_groups(fdas_plan p, const float *x, bool ragged, const Batch
         while (j < B.groups.size() && B.groups[j].g.nsamp == B.groups[i].g.nsamp) nb += B.groups[j++].nb;
         const int v0 = B.groups[i].vbase;
         TRY(run_spectrum(p, x, ragged ? p->d_offs + v0 : nullptr, B.groups[i].g.nsamp, nb, v0, st));
-        for (; i < j; ++i) {
-            const Group &G = B.groups[i];
-            const Bank *bk = nullptr;
-            TRY(get_bank(p, G.zmax, dz, G.cfg.L, &bk));
-            TRY(run_chunks(p, G.g, *bk, G.cfg, numharm, G.nb, G.vbase, false, st));
+        i = j;
+    }
+    for (const Wave &X : W.waves) {
+        for (const WorkItem &it : X.items) TRY(launch_item_k4(p, it, st));
+        if (X.nlist > 1) {
+            hipEvent_t e = p->begin(st);
+            HIPTRY(p, launch_harmsum_bounded_list(p->d_hitems + X.list0, p->d_hstarts + X.starts0, X.nlist, X.runs,
+                                                  numharm, p->d_thr, st));
+            p->end(3, e, st);
         }
+        for (const WorkItem &it : X.items)
+            if (!it.bounded || X.nlist < 2) TRY(launch_item_k5(p, it, numharm, st));
+        for (const WorkItem &it : X.items) TRY(launch_item_k6(p, it, numharm, st));
     }
     // significance of every record of the call, in one launch
     hipEvent_t e = p->begin(st);
@@ -835,12 +1006,15 @@ fdas_status enqueue_groups(fdas_plan p, const float *x, bool ragged, const Batch
 fdas_status run_batch(fdas_plan p, const float *x, bool ragged, const Batch &B, double dz, int numharm,
                       const std::string &key, fdas_cand *out, int64_t cap, int64_t *n_total, hipStream_t st) {
     const bool use_graph = p->opts.graph && !p->opts.profile;
+    // every bank, row table and work list of the batch exists before any capture
+    WavePlan W;
+    TRY(plan_waves(p, B, dz, numharm, W));
+    TRY(upload_lists(p, W, st));
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (use_graph) {
             if (p->graph_key != key || !p->graph) {
                 drop_graph(p);
                 if (!p->cap_st) HIPTRY(p, hipStreamCreateWithFlags(&p->cap_st, hipStreamNonBlocking));
-                // every bank and table of the batch must exist before capture
                 if (p->opts.norm == FDAS_NORM_LOCAL) {
                     for (size_t i = 0; i < B.groups.size();) {
                         size_t j = i;
@@ -853,15 +1027,9 @@ fdas_status run_batch(fdas_plan p, const float *x, bool ragged, const Batch &B, 
                         i = j;
                     }
                 }
-                for (const auto &G : B.groups) {
-                    const Bank *bk = nullptr;
-                    TRY(get_bank(p, G.zmax, dz, G.cfg.L, &bk));
-                    RowBlocks rb;
-                    TRY(get_rows(p, G.g.NZ, zgroups_of(G.g.NZ), G.cfg.bz, numharm, G.cfg.pair != 0, rb));
-                }
                 HIPTRY(p, hipStreamBeginCapture(p->cap_st, hipStreamCaptureModeThreadLocal));
                 p->capturing = true;
-                const fdas_status s = enqueue_groups(p, x, ragged, B, dz, numharm, p->cap_st);
+                const fdas_status s = enqueue_groups(p, x, ragged, B, W, numharm, p->cap_st);
                 p->capturing = false;
                 hipGraph_t gdef = nullptr;
                 const hipError_t e = hipStreamEndCapture(p->cap_st, &gdef);
@@ -876,7 +1044,7 @@ fdas_status run_batch(fdas_plan p, const float *x, bool ragged, const Batch &B, 
             }
             HIPTRY(p, hipGraphLaunch(p->graph, st));
         } else {
-            TRY(enqueue_groups(p, x, ragged, B, dz, numharm, st));
+            TRY(enqueue_groups(p, x, ragged, B, W, numharm, st));
         }
         bool regrow = false;
         const fdas_status s = finish(p, B, dz, !ragged, out, cap, n_total, st, &regrow);
@@ -989,7 +1157,8 @@ void fdas_plan_destroy(fdas_plan p) {
     for (auto &t : p->tables) (void)hipFree(t.d);
     for (auto &t : p->ltabs) (void)hipFree(t.second.first);
     void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_med, p->d_thr, p->d_state, p->d_offs,
-                   p->d_plane, p->d_maxv, p->d_zarg, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow, p->d_dd[0], p->d_dd[1], p->d_delays, p->d_csum, p->d_cpad, p->d_lmed};
+                   p->d_plane, p->d_maxv, p->d_zarg, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow, p->d_dd[0], p->d_dd[1], p->d_delays, p->d_csum, p->d_cpad, p->d_lmed,
+                   p->d_hitems, p->d_hstarts};
     for (void *q : dev)
         if (q) (void)hipFree(q);
     for (auto &t : p->ev_pending) {
@@ -997,7 +1166,8 @@ void fdas_plan_destroy(fdas_plan p) {
         p->ev_pool.push_back(std::get<2>(t));
     }
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-    void *host[] = {p->h_state, p->h_small, p->h_rec, p->h_offs, p->h_rpts, p->h_rpow, p->h_delays};
+    void *host[] = {p->h_state, p->h_small, p->h_rec, p->h_offs, p->h_rpts, p->h_rpow, p->h_delays,
+                    p->h_hitems, p->h_hstarts};
     for (void *q : host)
         if (q) (void)hipHostFree(q);
     if (cur >= 0) (void)hipSetDevice(cur);

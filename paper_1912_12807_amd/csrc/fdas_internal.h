@@ -176,6 +176,35 @@ hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t ser
                                   const float *thr_dev, float *maxv, int16_t *zarg, int64_t mpitch,
                                   hipStream_t st);
 
+// One entry of a bounded-sum work list: the arguments of
+// launch_harmsum_bounded for one set of series (its plane, block maxima and
+// maxima regions), plus its place in the merged launch. A work list lets one
+// launch cover the planes of several groups of a ragged batch, whose separate
+// launches each end in a partly idle tail.
+struct HarmItem {
+    const float *plane;
+    int64_t pitch, sstride;
+    const bmax_t *pyr;
+    int64_t psstride, ppitch;
+    const int32_t *blk_lo, *frange;
+    float *maxv;
+    int16_t *zarg;
+    int64_t mpitch, NR, rlo;
+    int64_t tiles_per_series;   // set by harm_items_layout
+    int64_t ntiles;             // set by harm_items_layout
+    int32_t nblk, Z, pair, nseries;
+};
+// Checks every item as launch_harmsum_bounded checks its arguments, fills in
+// the tile counts and writes starts[0..n]: the merged launch gives each XCD
+// (workgroup id mod 8) one contiguous run of starts[i+1] - starts[i] tiles
+// of item i, items in list order. Returns starts[n] (tiles per XCD), or -1 if
+// an item is invalid.
+int64_t harm_items_layout(HarmItem *items, int n, int numharm, int64_t *starts);
+// The merged bounded sums over a work list already in device memory
+// (items_dev[n], starts_dev[n + 1] from harm_items_layout; runs = starts[n]).
+hipError_t launch_harmsum_bounded_list(const HarmItem *items_dev, const int64_t *starts_dev, int n,
+                                       int64_t runs, int numharm, const float *thr_dev, hipStream_t st);
+
 // K6: ordered compaction of maxv > thr[stage] into records in (b, s, c) order,
 // with the drift index from zarg.
 // The batch may be processed in series chunks: state[0] (device int64) is the

@@ -203,26 +203,19 @@ __device__ __forceinline__ uint16_t load_bits_at(const bmax_t *base, uint32_t by
     return *reinterpret_cast<const bmax_t *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
+// Tile g of one set of series: series group g / tiles_per_series (SB series),
+// 256 columns from (g mod tiles_per_series) * 256.
 template <int NH>
-__global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ plane, int64_t pitch,
-                                                    int64_t sstride, const bmax_t *__restrict__ pyr,
-                                                    int64_t psstride, const int32_t *__restrict__ blk_lo,
-                                                    const int32_t *__restrict__ frange, int nblk,
-                                                    int64_t NR, int64_t rlo, int Z,
-                                                    const float *__restrict__ thr,
-                                                    float *__restrict__ maxv, int16_t *__restrict__ zarg,
-                                                    int64_t mpitch, int64_t tiles_per_series,
-                                                    int64_t total_tiles, int pair, int64_t ppitch, int nseries) {
+__device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane, int64_t pitch,
+                                                int64_t sstride, const bmax_t *__restrict__ pyr,
+                                                int64_t psstride, const int32_t *__restrict__ blk_lo,
+                                                const int32_t *__restrict__ frange, int nblk, int64_t NR,
+                                                int64_t rlo, int Z, const float *__restrict__ thr,
+                                                float *__restrict__ maxv, int16_t *__restrict__ zarg,
+                                                int64_t mpitch, int64_t tiles_per_series, int64_t g, int pair,
+                                                int64_t ppitch, int nseries) {
     constexpr int NS = Stages<NH>::NS;
     constexpr int SB = BoundCfg<NH>::SB;
-
-    // each XCD (workgroup id mod 8) takes a contiguous run of (series group,
-    // column tile) items: neighbouring tiles read overlapping fraction strips
-    // through its L2
-    const int64_t w = blockIdx.x;
-    const int64_t per_xcd = (total_tiles + 7) / 8;
-    const int64_t g = (w & 7) * per_xcd + (w >> 3);
-    if (g >= total_tiles) return;
     const int grp = (int)(g / tiles_per_series);
     const int b0 = grp * SB;
     const int64_t c = (g - (int64_t)grp * tiles_per_series) * 256 + threadIdx.x;
@@ -445,6 +438,63 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
             za[s * mpitch] = (int16_t)(valid[s] ? (azp[m][s >> 1] >> (16u * (s & 1))) & 0xffffu : 0u);
         }
     }
+}
+
+template <int NH>
+__global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ plane, int64_t pitch,
+                                                    int64_t sstride, const bmax_t *__restrict__ pyr,
+                                                    int64_t psstride, const int32_t *__restrict__ blk_lo,
+                                                    const int32_t *__restrict__ frange, int nblk,
+                                                    int64_t NR, int64_t rlo, int Z,
+                                                    const float *__restrict__ thr,
+                                                    float *__restrict__ maxv, int16_t *__restrict__ zarg,
+                                                    int64_t mpitch, int64_t tiles_per_series,
+                                                    int64_t total_tiles, int pair, int64_t ppitch, int nseries) {
+    // each XCD (workgroup id mod 8) takes a contiguous run of (series group,
+    // column tile) items: neighbouring tiles read overlapping fraction strips
+    // through its L2
+    const int64_t w = blockIdx.x;
+    const int64_t per_xcd = (total_tiles + 7) / 8;
+    const int64_t g = (w & 7) * per_xcd + (w >> 3);
+    if (g >= total_tiles) return;
+    harm_bound_tile<NH>(plane, pitch, sstride, pyr, psstride, blk_lo, frange, nblk, NR, rlo, Z, thr, maxv, zarg,
+                        mpitch, tiles_per_series, g, pair, ppitch, nseries);
+}
+
+// A pointer read from memory is generic for the compiler (flat loads with
+// 64-bit lane addresses); this marks it as global memory again.
+template <typename T>
+__device__ __forceinline__ T *global_ptr(T *p) {
+    typedef __attribute__((address_space(1))) T global_T;
+    return (T *)(global_T *)(uintptr_t)p;
+}
+
+// The same over a work list: the XCD of workgroup w (w mod 8) walks its runs
+// of every item in list order (the host puts the items with the most drift
+// blocks first, so the launch ends on cheap tiles); item i's run on XCD x is
+// its tiles x run_i ... (x + 1) run_i - 1, so each XCD still sweeps
+// neighbouring tiles. The item of a workgroup is found by bisection of the
+// run starts (wave-uniform scalar loads).
+template <int NH>
+__global__ __launch_bounds__(256) void k_harm_bound_list(const HarmItem *__restrict__ items,
+                                                         const int64_t *__restrict__ starts, int n,
+                                                         const float *__restrict__ thr) {
+    const int64_t w = blockIdx.x;
+    const int64_t l = w >> 3;
+    int lo = 0, hi = n;   // starts[lo] <= l < starts[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (starts[mid] <= l) lo = mid;
+        else hi = mid;
+    }
+    const HarmItem &it = items[lo];
+    const int64_t run = starts[lo + 1] - starts[lo];
+    const int64_t g = (w & 7) * run + (l - starts[lo]);
+    if (g >= it.ntiles) return;
+    harm_bound_tile<NH>(global_ptr(it.plane), it.pitch, it.sstride, global_ptr(it.pyr), it.psstride,
+                        global_ptr(it.blk_lo), global_ptr(it.frange), it.nblk, it.NR, it.rlo, it.Z, thr,
+                        global_ptr(it.maxv), global_ptr(it.zarg), it.mpitch, it.tiles_per_series, g, it.pair,
+                        it.ppitch, it.nseries);
 }
 
 // Block maxima of a caller-supplied plane (what K4 writes while it builds the
@@ -700,6 +750,56 @@ hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t ser
     default: return hipErrorInvalidValue;
     }
 #undef FDAS_BOUND
+    return hipGetLastError();
+}
+
+template <int NH>
+static void launch_bound_list_nh(const HarmItem *items, const int64_t *starts, int n, int64_t runs,
+                                 const float *thr, hipStream_t st) {
+    hipLaunchKernelGGL(k_harm_bound_list<NH>, dim3((unsigned)(8 * runs)), dim3(256), 0, st, items, starts, n, thr);
+}
+
+int64_t harm_items_layout(HarmItem *items, int n, int numharm, int64_t *starts) {
+    int sb = 0;
+    switch (numharm) {
+    case 1: sb = BoundCfg<1>::SB; break;
+    case 2: sb = BoundCfg<2>::SB; break;
+    case 4: sb = BoundCfg<4>::SB; break;
+    case 8: sb = BoundCfg<8>::SB; break;
+    case 16: sb = BoundCfg<16>::SB; break;
+    case 32: sb = BoundCfg<32>::SB; break;
+    default: return -1;
+    }
+    if (n < 1) return -1;
+    starts[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        HarmItem &it = items[i];
+        if (!it.plane || it.nseries < 1 || it.mpitch < it.NR || (it.mpitch & 15) ||
+            (it.mpitch + 255) / 256 * it.nseries > 0x7ffffff0LL || !it.pyr || !it.blk_lo || !it.frange ||
+            it.nblk < 1 || bounded_table_bytes(it.nblk, numharm) > kBoundTableMax ||
+            it.psstride > kMaxPyrSeriesStride || !it.maxv || !it.zarg || it.Z < 0 || it.Z > 32767 ||
+            (it.ppitch & 31) || it.ppitch < (it.pair ? it.NR / 2 : it.NR) || it.psstride < it.nblk * it.ppitch)
+            return -1;
+        it.tiles_per_series = (it.mpitch + 255) / 256;
+        it.ntiles = it.tiles_per_series * ((it.nseries + sb - 1) / sb);
+        starts[i + 1] = starts[i] + (it.ntiles + 7) / 8;
+    }
+    return starts[n] > 0x0fffffffLL ? -1 : starts[n];
+}
+
+hipError_t launch_harmsum_bounded_list(const HarmItem *items_dev, const int64_t *starts_dev, int n,
+                                       int64_t runs, int numharm, const float *thr_dev, hipStream_t st) {
+    if (n < 1 || runs < 1 || runs > 0x0fffffffLL || !items_dev || !starts_dev || !thr_dev)
+        return hipErrorInvalidValue;
+    switch (numharm) {
+    case 1: launch_bound_list_nh<1>(items_dev, starts_dev, n, runs, thr_dev, st); break;
+    case 2: launch_bound_list_nh<2>(items_dev, starts_dev, n, runs, thr_dev, st); break;
+    case 4: launch_bound_list_nh<4>(items_dev, starts_dev, n, runs, thr_dev, st); break;
+    case 8: launch_bound_list_nh<8>(items_dev, starts_dev, n, runs, thr_dev, st); break;
+    case 16: launch_bound_list_nh<16>(items_dev, starts_dev, n, runs, thr_dev, st); break;
+    case 32: launch_bound_list_nh<32>(items_dev, starts_dev, n, runs, thr_dev, st); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -102,6 +102,23 @@ def test_ragged_equals_per_series_calls(fdas_gpu, ragged):
         assert np.array_equal(g[g["series"] == i], one), i
 
 
+def test_ragged_waves_in_small_workspace(fdas_gpu, ragged):
+    """A workspace of two of the largest planes splits the batch into several
+    waves (groups into chunks); the merged harmonic-sum launches of each wave
+    give the records of the one-wave search, eagerly and under graph replay."""
+    wl, buf, offs = ragged
+    d = _cuda(buf)
+    ref = _plan(fdas_gpu, wl).search_ragged(d, offs, wl.nsamp, wl.tsamp, wl.zmax, sigma=wl.sigma, cap=1 << 18)
+    nz = 2 * int(round(max(wl.zmax) / wl.dz)) + 1
+    pitch = -(-max(wl.nsamp) // 64) * 64
+    for graph in (0, 1):
+        small = _plan(fdas_gpu, wl, max_workspace_bytes=2 * nz * pitch * 4, graph=graph)
+        assert small.info()["chunk_series"] == 2
+        for _ in range(2):
+            g = small.search_ragged(d, offs, wl.nsamp, wl.tsamp, wl.zmax, sigma=wl.sigma, cap=1 << 18)
+            assert np.array_equal(g, ref), graph
+
+
 def test_ragged_series_order_and_offsets_are_free(fdas_gpu, ragged):
     """A permuted packing with gaps gives the same records, relabelled."""
     wl, buf, offs = ragged
