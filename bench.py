@@ -277,6 +277,66 @@ def write_traffic(res, workload, f_scale, w_scale, seg_len=None):
         json.dump(data, fh, indent=1, sort_keys=True)
 
 
+def counters_summary(csvs, title: str, command: str, bench_log: str) -> str:
+    """Markdown table of per-launch hardware counters of the plane and
+    harmonic-sum kernels from rocprofv3 --pmc CSVs (one per counter pass), with
+    the derived rates used in the design notes. Cells per launch come from the
+    bench line of the same workload (both kernels cover one series chunk)."""
+    import csv
+    import collections
+    cells = None
+    for line in open(bench_log):
+        if line.startswith("{"):
+            cells = json.loads(line)["roofline"].get("cells_per_launch")
+    val = collections.defaultdict(lambda: collections.defaultdict(list))
+    dur = collections.defaultdict(dict)
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            k = _kernel_key(r["Kernel_Name"])
+            if not (k.startswith("fdas::k_corr_power") or k.startswith("fdas::k_harm_bound")):
+                continue
+            val[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            dur[k][(path, r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    out = [f"# Hardware counters per launch: {title}", "", "Commands (repository root on the GPU box as $REPO):", "",
+           "```", command, "```", "",
+           "Averages per launch over the dispatches of every pass. GRBM_GUI_ACTIVE is summed over the 8 XCDs and "
+           "SQ_BUSY_CYCLES over the 32 shader engines; 'GRBM clock' = GRBM_GUI_ACTIVE / 8 / launch time. VALU "
+           "per cell = SQ_INSTS_VALU x 64 lanes / plane cells of the launch "
+           f"({cells:.4g} cells per launch). L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS).", ""]
+    for k in sorted(val):
+        c = {n: sum(v) / len(v) for n, v in val[k].items()}
+        t = sum(dur[k].values()) / len(dur[k])
+        out += [f"## `{k}`", "", f"launch time under the counters: {t * 1e3:.3f} ms", "",
+                "| counter | per launch |", "|---|---|"]
+        out += [f"| {n} | {c[n]:.4g} |" for n in sorted(c)]
+        der = []
+        g = c.get("GRBM_GUI_ACTIVE")
+        if g:
+            der.append(("GRBM clock (GHz)", g / 8 / t / 1e9))
+        if "SQ_INSTS_VALU" in c:
+            if cells:
+                der.append(("VALU instructions per cell (lanes)", c["SQ_INSTS_VALU"] * 64 / cells))
+            if c.get("SQ_WAVES"):
+                der.append(("VALU instructions per wave", c["SQ_INSTS_VALU"] / c["SQ_WAVES"]))
+            if g:
+                der.append(("VALU instructions per SIMD per GRBM cycle", c["SQ_INSTS_VALU"] / (1024 * g / 8)))
+        if "SQ_BUSY_CYCLES" in c and g:
+            der.append(("SQ busy fraction", c["SQ_BUSY_CYCLES"] / (4 * g)))
+        if "SQ_ACTIVE_INST_VALU" in c and g:
+            der.append(("VALU active cycles per SIMD / GRBM cycles", c["SQ_ACTIVE_INST_VALU"] / (1024 * g / 8)))
+        if "SQ_INSTS_VMEM_RD" in c and c.get("SQ_WAVES"):
+            der.append(("vector memory reads per wave", c["SQ_INSTS_VMEM_RD"] / c["SQ_WAVES"]))
+        if "TCC_HIT_sum" in c and "TCC_MISS_sum" in c:
+            der.append(("L2 hit rate", c["TCC_HIT_sum"] / max(1.0, c["TCC_HIT_sum"] + c["TCC_MISS_sum"])))
+        if "TCP_TCC_READ_REQ_LATENCY_sum" in c and c.get("TCP_TCC_READ_REQ_sum"):
+            der.append(("mean L1-to-L2 read latency (cycles)",
+                        c["TCP_TCC_READ_REQ_LATENCY_sum"] / c["TCP_TCC_READ_REQ_sum"]))
+        if der:
+            out += ["", "| derived | value |", "|---|---|"] + [f"| {n} | {v:.4g} |" for n, v in der]
+        out.append("")
+    return "\n".join(out)
+
+
 def launch_tails_summary(trace_csv: str, title: str, command: str, steps: int) -> str:
     """Markdown summary of what grouped launches cost beyond their work, from a
     rocprofv3 --kernel-trace CSV of eager searches.
@@ -356,6 +416,9 @@ def main():
                     help="write a markdown summary of a rocprofv3 kernel-stats CSV and exit")
     ap.add_argument("--summary-title", default="",
                     help="workload description for --stats-summary (default: the config's workload name)")
+    ap.add_argument("--counters-summary", nargs="+", metavar="ARG",
+                    help="OUT_MD COMMAND BENCH_LOG CSV [CSV ...]: per-launch counters of the plane and "
+                         "harmonic-sum kernels (title from --summary-title)")
     ap.add_argument("--tails-summary", nargs=4, metavar=("TRACE_CSV", "OUT_MD", "COMMAND", "SEARCHES"),
                     help="write the launch-tail summary of a rocprofv3 kernel trace and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_MD", "COMMAND"),
@@ -374,6 +437,14 @@ def main():
         title = args.summary_title or _workload(args.config).name
         with open(out_md, "w") as fh:
             fh.write(launch_tails_summary(csv_path, title, cmd, int(n)))
+        return
+    if args.counters_summary:
+        if len(args.counters_summary) < 4:
+            ap.error("--counters-summary needs OUT_MD COMMAND BENCH_LOG CSV [CSV ...]")
+        out_md, cmd, log = args.counters_summary[:3]
+        title = args.summary_title or _workload(args.config).name
+        with open(out_md, "w") as fh:
+            fh.write(counters_summary(args.counters_summary[3:], title, cmd, log))
         return
     if args.pmc_summary:
         fcsv, wcsv, out_md, cmd = args.pmc_summary

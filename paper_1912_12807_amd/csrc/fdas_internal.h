@@ -129,6 +129,9 @@ void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int
 // Host table of the row blocks each harmonic fraction of each block reads.
 void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
                      const std::vector<int32_t> &of_row, std::vector<int32_t> &frange);
+// Fourth word of a raw buffer resource on this GPU family (32-bit data
+// format; the base, stride 0 and the byte range come from the caller).
+constexpr int kBufferRsrcWord3 = 0x00020000;
 // Block maxima are stored as IEEE half bits rounded upward (+inf above the
 // largest half), so every stored value still bounds the powers of its block.
 using bmax_t = uint16_t;

@@ -25,10 +25,6 @@
 
 namespace fdas {
 
-// Fourth word of a raw buffer resource on this GPU family (32-bit data
-// format; the base, stride 0 and the byte range come from the caller).
-static constexpr int kBufferRsrcWord3 = 0x00020000;
-
 template <int L>
 struct Corr {
     static constexpr int T = L / 8;          // threads per workgroup
@@ -274,11 +270,18 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
                                                           t_row + p * (int)sizeof(float),
                                                           2 * q * T * (int)sizeof(float), 0);
                 }
+                // powers are >= +0, so their bit patterns order like their
+                // values: an integer maximum needs no NaN canonicalisation
+                // (a float maximum costs two instructions per power here)
                 if constexpr (PYR == 2) {
-                    m0[q] = fmaxf(m0[q], pw);     // both parities: fused into 3-input maxima
+                    // both parities in one 3-input maximum (the parity-0 power
+                    // waits in pw0 anyway when pairs are stored)
+                    if constexpr (kPairStore) {
+                        if (p == 1) m0[q] = max_nonneg(m0[q], max_nonneg(pw0[q], pw));
+                    } else {
+                        m0[q] = max_nonneg(m0[q], pw);
+                    }
                 } else if constexpr (PYR == 1) {
-                    // powers are >= +0, so their bit patterns order like their
-                    // values: an integer maximum needs no NaN canonicalisation
                     if (p == 0) m0[q] = max_nonneg(m0[q], pw);
                     else m1[q] = max_nonneg(m1[q], pw);
                 }
