@@ -286,17 +286,21 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
         const int kend = nblk - k0 < 64 ? nblk - k0 : 64;
         for (int kk = 0; kk < kend; ++kk) {
             const int32_t *fr = frange + (k0 + kk) * NH;
-            // Up to 8 harmonics: the first row block of every range, and the
-            // second only where the range has one (a wave-uniform test). The
+            // The first row block of every range, and the second only where
+            // the range has one (a wave-uniform test; about a third of the
+            // ranges at 6-row blocks and 16 harmonics). The block's ranges are
+            // read before the first test: inside the tests each would be a
+            // scalar load of its own that the next gathers wait for. The
             // gathers keep their raw half bits, so no conversion sits in a
             // branch where it would wait for all earlier loads, and both
             // blocks' bits merge by an integer maximum (non-negative halves
-            // order like their bits). Above 8 harmonics that code holds too
-            // many registers, and both row blocks are gathered unconditionally
-            // (the same one twice when e = a).
+            // order like their bits).
             float B[SB][NH];
             int wide = 0;
-            if constexpr (NH <= 8) {
+            {
+                int32_t fv[NH];
+#pragma unroll
+                for (int j = 0; j < NH; ++j) fv[j] = fr[j];
                 uint16_t Bb[SB][NH], Cb[SB][NH];
                 // a zero the compiler cannot see through: with a literal 0 it
                 // folds the merge into the branch, where it waits for every
@@ -304,7 +308,7 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
                 const uint16_t zero = (uint16_t)__builtin_amdgcn_mbcnt_lo(0u, 0u);
 #pragma unroll
                 for (int j = 0; j < NH; ++j) {
-                    const int32_t f = fr[j];
+                    const int32_t f = fv[j];
                     const int n = f >> 24;
                     wide |= n > 1;
                     const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
@@ -323,26 +327,6 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
 #pragma unroll
                     for (int j = 0; j < NH; ++j)
                         B[m][j] = half_bits_to_float(Bb[m][j] > Cb[m][j] ? Bb[m][j] : Cb[m][j]);
-                }
-            } else {
-                float C[SB][NH];
-#pragma unroll
-                for (int j = 0; j < NH; ++j) {
-                    const int32_t f = fr[j];
-                    const int n = f >> 24;
-                    wide |= n > 1;
-                    const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
-                    const uint32_t o1 = n > 0 ? o0 + rowb : o0;
-#pragma unroll
-                    for (int m = 0; m < SB; ++m) {
-                        B[m][j] = load_at(yb[m], o0);
-                        C[m][j] = load_at(yb[m], o1);
-                    }
-                }
-#pragma unroll
-                for (int m = 0; m < SB; ++m) {
-#pragma unroll
-                    for (int j = 0; j < NH; ++j) B[m][j] = fmaxf(B[m][j], C[m][j]);
                 }
             }
             if (wide) {
