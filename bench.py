@@ -151,14 +151,29 @@ def stream_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:
 
 
 def _cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo reports it: model name, clock, sockets and
+    logical CPUs, and how many of them this process may use (on a virtual
+    machine the model name can be generic)."""
+    name, mhz, sockets, logical = "", "", set(), 0
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "processor":
+                    logical += 1
+                elif key == "model name" and not name:
+                    name = val
+                elif key == "cpu MHz" and not mhz:
+                    mhz = val
+                elif key == "physical id":
+                    sockets.add(val)
     except OSError:
-        pass
-    return ""
+        return ""
+    usable = len(os.sched_getaffinity(0))
+    clock = f", {float(mhz) / 1e3:.2f} GHz reported" if mhz else ""
+    return (f"{name}{clock}, {len(sockets) or 1} socket(s), {logical} logical CPUs, "
+            f"{usable} usable by this process")
 
 
 def cpu_baseline_ragged(config: int, wl, cells_of, max_cores: int = 16, max_nsamp: int = 1 << 17):
@@ -302,7 +317,10 @@ def counters_summary(csvs, title: str, command: str, bench_log: str) -> str:
            "Averages per launch over the dispatches of every pass. GRBM_GUI_ACTIVE is summed over the 8 XCDs and "
            "SQ_BUSY_CYCLES over the 32 shader engines; 'GRBM clock' = GRBM_GUI_ACTIVE / 8 / launch time. VALU "
            "per cell = SQ_INSTS_VALU x 64 lanes / plane cells of the launch "
-           f"({cells:.4g} cells per launch). L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS).", ""]
+           f"({cells:.4g} cells per launch). L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS). Busy fractions "
+           "are per unit over the GRBM cycles of the launch (1024 SIMDs, 256 scalar units and 256 texture "
+           "addressers); the counters come from separate passes, so rates that mix passes assume the "
+           "passes ran alike (their launch times agree within a few per cent).", ""]
     for k in sorted(val):
         c = {n: sum(v) / len(v) for n, v in val[k].items()}
         t = sum(dur[k].values()) / len(dur[k])
@@ -320,6 +338,16 @@ def counters_summary(csvs, title: str, command: str, bench_log: str) -> str:
                 der.append(("VALU instructions per wave", c["SQ_INSTS_VALU"] / c["SQ_WAVES"]))
             if g:
                 der.append(("VALU instructions per SIMD per GRBM cycle", c["SQ_INSTS_VALU"] / (1024 * g / 8)))
+            if g:
+                der.append(("VALU busy fraction (4 cycles per wave64 instruction)",
+                            4 * c["SQ_INSTS_VALU"] / (1024 * g / 8)))
+        if "SQ_INSTS_SALU" in c and g:
+            der.append(("SALU busy fraction (one scalar unit per CU)", c["SQ_INSTS_SALU"] / (256 * g / 8)))
+        if "TA_BUSY_avr" in c and g:
+            der.append(("texture addresser busy fraction", c["TA_BUSY_avr"] / (g / 8)))
+            if "SQ_INSTS_VMEM_RD" in c:
+                der.append(("texture addresser cycles per vector memory read",
+                            c["TA_BUSY_avr"] / (c["SQ_INSTS_VMEM_RD"] / 256)))
         if "SQ_BUSY_CYCLES" in c and g:
             der.append(("SQ busy fraction", c["SQ_BUSY_CYCLES"] / (4 * g)))
         if "SQ_ACTIVE_INST_VALU" in c and g:
