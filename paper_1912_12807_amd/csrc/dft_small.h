@@ -23,6 +23,22 @@ __device__ __forceinline__ float half_bits_to_float(uint16_t u) {
     return (float)__builtin_bit_cast(_Float16, u);
 }
 
+// 8-bit code of an upper bound of x >= 0: code c stands for
+// (1 + (c mod 32) / 32) 2^(c / 32), i.e. 1 to 252 with five mantissa bits
+// (the float whose bits are c << 18 above those of 1.0). x <= 1 gives 0 (1.0);
+// above 1 the code is the float's top five mantissa bits, stepped up once
+// when a lower bit is set, so code_value(bound_code(x)) >= x for x <= 252;
+// larger values, +inf and NaN saturate at 255 (252). A bound built from such
+// values still exceeds any threshold below 252 wherever the exact value does.
+__device__ __forceinline__ uint32_t bound_code(float x) {
+    // ceil((bits(x) - bits(1.0)) / 2^18), clamped to 0..255: negative (x < 1)
+    // gives 0, +inf and NaN land far above 255
+    const int32_t c = (int32_t)(__float_as_uint(x) - 0x3f7c0001u) >> 18;
+    return (uint32_t)(c < 0 ? 0 : c > 255 ? 255 : c);
+}
+__device__ __forceinline__ float code_value(uint32_t c) { return __uint_as_float((c << 18) + 0x3f800000u); }
+constexpr float kCodeMax = 252.0f;   // code_value(255)
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 // Complex products with the fused multiply-adds written out, so that every

@@ -139,6 +139,7 @@ struct Bank {
 
 struct RowTable {
     int NZ = -1, G = -1, bz = -1, nh = -1;
+    int64_t ppitch = -1;
     int32_t *d = nullptr;
     int nblk = 0;
     uint64_t used = 0;
@@ -428,25 +429,30 @@ fdas_status get_bank(fdas_plan p, double zmax, double dz, int L, const Bank **ou
     return FDAS_OK;
 }
 
-// Row-block tables for the bounded harmonic sums, cached per geometry:
-// lo[nblk + 1], of_row[NZ], frange[nblk][numharm] in one device buffer.
-fdas_status get_rows(fdas_plan p, int NZ, int G, int bz, int numharm, bool pair, RowBlocks &rb) {
+// Row-block tables for the bounded harmonic sums, cached per geometry and
+// maxima pitch: lo[nblk + 1], of_row[NZ], frange[nblk][numharm] and the bound
+// test's gather table for code pairs [nblk][2 numharm + 2] in one device
+// buffer.
+fdas_status get_rows(fdas_plan p, int NZ, int G, int bz, int numharm, bool pair, int64_t ppitch, RowBlocks &rb) {
     RowTable *t = nullptr;
     for (auto &x : p->tables)
-        if (x.NZ == NZ && x.G == G && x.bz == bz && x.nh == numharm) t = &x;
+        if (x.NZ == NZ && x.G == G && x.bz == bz && x.nh == numharm && x.ppitch == ppitch) t = &x;
     if (!t) {
-        std::vector<int32_t> lo, of_row, fr;
+        std::vector<int32_t> lo, of_row, fr, bo;
         row_blocks(NZ, G, bz, lo, of_row);
         fraction_ranges(NZ, numharm, lo, of_row, fr);
+        bound_offsets(numharm, fr, ppitch, bo);
         std::vector<int32_t> all(lo);
         all.insert(all.end(), of_row.begin(), of_row.end());
         all.insert(all.end(), fr.begin(), fr.end());
+        all.insert(all.end(), bo.begin(), bo.end());
         evict<RowTable>(p, p->tables, kMaxTables, [](RowTable &r) -> void * { return r.d; });
         RowTable n;
         n.NZ = NZ;
         n.G = G;
         n.bz = bz;
         n.nh = numharm;
+        n.ppitch = ppitch;
         n.nblk = (int)lo.size() - 1;
         TRY(dalloc(p, &n.d, (int64_t)all.size(), "row-block tables"));
         if (hipMemcpy(n.d, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
@@ -463,7 +469,9 @@ fdas_status get_rows(fdas_plan p, int NZ, int G, int bz, int numharm, bool pair,
     rb.frange = rb.of_row + NZ;
     rb.nblk = t->nblk;
     rb.frange_nh = numharm;
+    rb.table_ppitch = ppitch;
     rb.pair = pair;
+    rb.ppitch = ppitch;
     return FDAS_OK;
 }
 
@@ -573,8 +581,8 @@ fdas_status group_item(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
     it.vbase = vbase;
     it.pitch = round_up(g.NR, 64);
     it.sstride = (int64_t)g.NZ * it.pitch;
-    TRY(get_rows(p, g.NZ, it.cg.zgroups, cfg.bz, numharm, cfg.pair != 0, it.rb));
-    it.rb.ppitch = it.rb.pair ? it.pitch / 2 : it.pitch;
+    TRY(get_rows(p, g.NZ, it.cg.zgroups, cfg.bz, numharm, cfg.pair != 0, cfg.pair ? it.pitch / 2 : it.pitch,
+                 it.rb));
     it.psstride = (int64_t)it.rb.nblk * it.rb.ppitch;
     // K4 writes the block maxima whenever the buffer sized at plan creation
     // holds those of a chunk series. The exhaustive sums do not read them, but
@@ -923,7 +931,8 @@ fdas_status plan_waves(fdas_plan p, const Batch &B, double dz, int numharm, Wave
         X.list0 = (int)W.list.size();
         X.starts0 = (int)W.starts.size();
         for (const WorkItem *it : bi) {
-            if (it->rb.frange_nh != numharm) return p->fail(FDAS_E_DEVICE, "internal error: row table of another numharm");
+            if (it->rb.frange_nh != numharm || it->rb.table_ppitch != it->rb.ppitch)
+                return p->fail(FDAS_E_DEVICE, "internal error: row table of another numharm or pitch");
             HarmItem h{};
             h.plane = p->d_plane + it->plane_off;
             h.pitch = it->pitch;
@@ -1245,7 +1254,7 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     p->plane_cap = chunk * per_series;
     if ((s = dalloc(p, &p->d_plane, p->plane_cap, "power plane")) != FDAS_OK) return bail(s);
     // block maxima of every chunk series: blocks of >= kMinBlockRows rows
-    // (NZ / bz + 8 blocks at most, z groups cut blocks), per column
+    // (NZ / bz + 8 blocks at most, z groups cut blocks), 16 bits per column
     const int bzmin = o.harm_block ? o.harm_block : kMinBlockRows;
     p->min_bz = bzmin;
     p->pyr_cap = chunk * (int64_t)(g.NZ / bzmin + 9) * pitch;
@@ -1656,10 +1665,10 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
     // block maxima of the caller's plane for the bounded sums (row blocks as a
     // single z group; results do not depend on the partition)
     RowBlocks rb;
-    TRY(get_rows(p, g.NZ, 1, p->opts.harm_block ? p->opts.harm_block : default_block_rows(numharm), numharm,
-                 maxima_per_bin(p->opts.harm_pair, numharm), rb));
     // maxima rows padded like the search's (a multiple of 32 halves)
-    rb.ppitch = rb.pair ? round_up(g.NR, 64) / 2 : round_up(g.NR, 64);
+    const bool mpair = maxima_per_bin(p->opts.harm_pair, numharm);
+    TRY(get_rows(p, g.NZ, 1, p->opts.harm_block ? p->opts.harm_block : default_block_rows(numharm), numharm,
+                 mpair, mpair ? round_up(g.NR, 64) / 2 : round_up(g.NR, 64), rb));
     const int64_t psstride = (int64_t)rb.nblk * rb.ppitch;
     int64_t chunk = std::min<int64_t>(p->max_series, p->maxv_cap / (NS * mpitch));
     const bool bounded = !p->opts.harm_bound && bounded_table_bytes(rb.nblk, numharm) <= kBoundTableMax &&

@@ -118,10 +118,16 @@ struct RowBlocks {
     const int32_t *of_row = nullptr;  // NZ entries
     const int32_t *frange = nullptr;  // [nblk][frange_nh]: row blocks a..e that fraction j of
                                       // block k reads, packed a | (e - a) << 24
+    // frange is followed by the bound test's gather table for code pairs in
+    // rows of table_ppitch words (bound_offsets()), [nblk][2 frange_nh + 2]
     int nblk = 0;
     int frange_nh = 0;
-    bool pair = false;                // maxima per bin (both parities) instead of per column
-    int64_t ppitch = 0;               // halves per row block of the maxima (a multiple of 32)
+    int64_t table_ppitch = 0;
+    bool pair = false;                // maxima per bin (both parities, one half each) instead of
+                                      // per column (a 16-bit word each: the 8-bit codes of
+                                      // blocks k and k + 1)
+    int64_t ppitch = 0;               // 16-bit entries per row block of the maxima (a multiple
+                                      // of 32): pitch / 2 per bin, pitch per column
 };
 // Host construction of the row-block partition for NZ rows, G z groups and
 // blocks of at most bz rows (as even as possible inside each group).
@@ -129,6 +135,17 @@ void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int
 // Host table of the row blocks each harmonic fraction of each block reads.
 void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
                      const std::vector<int32_t> &of_row, std::vector<int32_t> &frange);
+// Host table of what the bound test of block k gathers for fraction j from
+// code pairs per column (maxima rows of ppitch 16-bit words): entry [k][j] is
+// the byte offset of row block a (the first of the fraction's range),
+// [k][numharm + j] the byte selector (v_perm) that keeps block a + 1's code
+// where the range has it (0x0c010c00) and drops it where the range is block a
+// alone (0x0c0c0c00), [k][2 numharm + 1] non-zero if some range has three or
+// more blocks. Maxima per bin are gathered by offsets the kernel derives from
+// frange.
+void bound_offsets(int numharm, const std::vector<int32_t> &frange, int64_t ppitch,
+                   std::vector<int32_t> &boff);
+constexpr int kBoundChunk = 64;   // blocks per pass of the bound test (one 64-bit hot mask)
 // Fourth word of a raw buffer resource on this GPU family (32-bit data
 // format; the base, stride 0 and the byte range come from the caller).
 constexpr int kBufferRsrcWord3 = 0x00020000;
@@ -140,13 +157,15 @@ using bmax_t = uint16_t;
 constexpr size_t kBoundTableMax = 48 * 1024;
 constexpr int64_t kMaxPyrSeriesStride = ((int64_t)1 << 31) - 1;   // halves
 inline size_t bounded_table_bytes(int nblk, int numharm) {
-    return (size_t)(nblk + 1 + (size_t)nblk * numharm) * sizeof(int32_t);
+    return (size_t)(nblk + 1 + (size_t)nblk * numharm + (size_t)nblk * (2 * numharm + 2)) * sizeof(int32_t);
 }
 
-// K4. If pyr is not null, K4 also writes the block maxima: pyr[b][k][c] = max
-// over the rows of block k of plane[b][row][c] (pitch = plane pitch), or with
-// rb.pair the maximum over columns 2i and 2i+1 at pyr[b][k][i] (pitch / 2),
-// rounded up to half precision.
+// K4. If pyr is not null, K4 also writes the block maxima, rounded up: with
+// rb.pair the maximum over the rows of block k and columns 2i and 2i+1 as a
+// half at pyr[b][k][i] (rows of pitch / 2 halves); otherwise, per column c, a
+// 16-bit word at pyr[b][k][c] (rows of pitch words) holding bound_code() of
+// the maxima of blocks k (low byte) and k + 1 (high byte; 0 for the last
+// block).
 hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *scale,
                              const float2 *bank, const CorrGeom &g, int nseries, float *plane,
                              int64_t pitch, int64_t series_stride, bmax_t *pyr,

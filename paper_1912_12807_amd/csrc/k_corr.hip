@@ -214,16 +214,22 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
     for (int q = 0; q < 8; ++q) S[q] = make_float2(S[q].x * sc, S[q].y * sc);
 
     float *out = plane + (int64_t)b * sstride + 2 * (ks - g.rlo);
-    // block-maxima row: pitch halves per block (PYR 1), pitch/2 (PYR 2)
+    // block-maxima row: pitch/2 halves per block (PYR 2: one half per bin);
+    // pitch 16-bit words (PYR 1: per column, the 8-bit codes of blocks k and
+    // k + 1)
     const int64_t ppitch = PYR == 2 ? pitch / 2 : pitch;
     bmax_t *pout = PYR ? pyr + (int64_t)b * psstride + (PYR == 2 ? 1 : 2) * (ks - g.rlo) : nullptr;
     int blk = 0, blk_end = 0;
     float m0[8], m1[8];
+    uint32_t pv[8];   // PYR 1: the previous block's codes of both columns of a bin
     if constexpr (PYR != 0) {
         blk = blk_of_row[z0];
         blk_end = blk_lo[blk + 1];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) m0[q] = m1[q] = 0.0f;
+        for (int q = 0; q < 8; ++q) {
+            m0[q] = m1[q] = 0.0f;
+            pv[q] = 0u;
+        }
     }
     // Kernel spectra and plane rows go through buffer resources: a
     // workgroup-uniform base and scalar offset plus the lane's fixed 32-bit
@@ -290,6 +296,15 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
         if constexpr (PYR != 0) {
             if (zi + 1 == blk_end) {
                 bmax_t *prow = pout + (int64_t)blk * ppitch;
+                // PYR 1 code pairs: word k of a column holds the codes of
+                // blocks k (low byte) and k + 1 (high byte; 0 above the last
+                // block). Block k's code goes to word k - 1 (high byte) and
+                // word k (low byte). Inside a z group one workgroup has both
+                // codes of a word and stores both columns' words of a bin as
+                // one 32-bit value, one block late; across a group boundary
+                // each group's workgroup stores its own bytes.
+                const bool first = blk_lo[blk] == z0;           // first block of the group
+                const bool last = zi + 1 == z1;                 // last block of the group
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int i = t + q * T;
@@ -297,8 +312,27 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
                         if constexpr (PYR == 2) {
                             prow[i] = bound_half(m0[q]);
                         } else {
-                            const uint32_t two = (uint32_t)bound_half(m0[q]) | ((uint32_t)bound_half(m1[q]) << 16);
-                            *reinterpret_cast<uint32_t *>(prow + 2 * i) = two;
+                            // columns 2i and 2i + 1: words 2i and 2i + 1 of the row
+                            // cur = c0 | c1 << 8; the bin's two words are the
+                            // bytes [p0, c0, p1, c1] of pv and cur (one permute)
+                            const uint32_t cur = bound_code(m0[q]) | (bound_code(m1[q]) << 8);
+                            uint8_t *w = reinterpret_cast<uint8_t *>(prow + 2 * i);
+                            uint8_t *wp = reinterpret_cast<uint8_t *>(prow - ppitch + 2 * i);
+                            if (!first) {
+                                *reinterpret_cast<uint32_t *>(wp) = __builtin_amdgcn_perm(cur, pv[q], 0x05010400u);
+                            } else if (z0 > 0) {
+                                wp[1] = (uint8_t)cur;
+                                wp[3] = (uint8_t)(cur >> 8);
+                            }
+                            if (last) {
+                                if (z1 == g.NZ) {
+                                    *reinterpret_cast<uint32_t *>(w) = __builtin_amdgcn_perm(0u, cur, 0x0c010c00u);
+                                } else {
+                                    w[0] = (uint8_t)cur;
+                                    w[2] = (uint8_t)(cur >> 8);
+                                }
+                            }
+                            pv[q] = cur;
                         }
                     }
                     m0[q] = m1[q] = 0.0f;
@@ -370,6 +404,28 @@ void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
     }
 }
 
+void bound_offsets(int numharm, const std::vector<int32_t> &frange, int64_t ppitch,
+                   std::vector<int32_t> &boff) {
+    const int nblk = (int)(frange.size() / numharm);
+    const int W = 2 * numharm + 2;
+    const uint32_t rowb = (uint32_t)ppitch * (uint32_t)sizeof(bmax_t);
+    boff.assign((size_t)nblk * W, 0);
+    for (int k = 0; k < nblk; ++k) {
+        int32_t *o = &boff[(size_t)k * W];
+        int32_t wide = 0;
+        for (int j = 0; j < numharm; ++j) {
+            const int32_t f = frange[(size_t)k * numharm + j];
+            const uint32_t a = (uint32_t)(f & 0xffffff), n = (uint32_t)f >> 24;
+            o[j] = (int32_t)(a * rowb);
+            // the code pair of block a holds a + 1's code in its high byte: a
+            // byte selector that keeps it where the range has a + 1
+            o[numharm + j] = n > 0 ? 0x0c010c00 : 0x0c0c0c00;
+            if (n > 1) wide = 1;
+        }
+        o[2 * numharm + 1] = wide;
+    }
+}
+
 template <int L>
 static void launch_l(const float2 *spec, int64_t spitch, const float *scale, const float2 *bank,
                      const CorrGeom &g, int nseries, float *plane, int64_t pitch, int64_t sstride,
@@ -392,7 +448,7 @@ hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *sc
     if ((int64_t)2 * g.NZ * g.L * 8 > 0x7fffffffLL || (int64_t)2 * g.Lv * 4 > 0x7fffffffLL)
         return hipErrorInvalidValue;
     if (nseries < 1 || g.nseg < 1 || g.Lv < 1 || (g.zgroups & (g.zgroups - 1)) || g.zgroups > 8 ||
-        g.zgroups < 1 || (pitch & 1) ||
+        g.zgroups < 1 || g.zgroups > g.NZ || (pitch & 1) ||
         (pyr && (!rb.lo || !rb.of_row || rb.nblk < 1 || rb.ppitch != (rb.pair ? pitch / 2 : pitch))))
         return hipErrorInvalidValue;
     const int64_t units = (int64_t)nseries * g.nseg;

@@ -41,6 +41,42 @@ __device__ __forceinline__ void stage_chain(const float *P, float *Ss) {
     }
 }
 
+// The same chain over the raw half bits of bounds: each step adds the half to
+// the FP32 sum with one mixed-precision fused multiply-add (h x 1 + S rounds
+// once, exactly as S + (float)h), so it orders the bounds exactly like
+// stage_chain and needs no separate conversions.
+template <int NH>
+__device__ __forceinline__ void stage_chain_h(const uint16_t *Ph, float *Ss) {
+    // a one the compiler cannot see through: with a literal 1 it turns the
+    // multiply-add back into a conversion and an addition
+    const float one = __uint_as_float(0x3f800000u | __builtin_amdgcn_mbcnt_lo(0u, 0u));
+    float S = half_bits_to_float(Ph[NH - 1]);
+    Ss[0] = S;
+    int s = 1;
+#pragma unroll
+    for (int h = 2; h <= NH; h *= 2, ++s) {
+#pragma unroll
+        for (int k = 1; k < h; k += 2) S = __builtin_fmaf(half_bits_to_float(Ph[k * (NH / h) - 1]), one, S);
+        Ss[s] = S;
+    }
+}
+
+// The larger of the two 8-bit codes of a 16-bit word w, the high one only
+// where the byte selector sel keeps it: the permute spreads the codes into
+// the two 16-bit halves of a register (sel 0x0c010c00; 0x0c0c0c00 zeroes the
+// high code) and one packed maximum compares them. Bits above the low half of
+// the result are not zero; code_half_bits drops them.
+__device__ __forceinline__ uint32_t max_code(uint32_t w, uint32_t sel) {
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    const u16x2 a = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(0u, w, sel));
+    const u16x2 m = __builtin_elementwise_max(a, __builtin_shufflevector(a, a, 1, 0));
+    return __builtin_bit_cast(uint32_t, m);
+}
+// Half bits of a code's value: (1 + (c mod 32) / 32) 2^(c / 32) has half
+// exponent c / 32 + 15 and mantissa (c mod 32) << 5, i.e. (c << 5) + 0x3c00
+// (c <= 255 keeps it below 0x7c00, and bits of c above 15 leave the half).
+__device__ __forceinline__ uint16_t code_half_bits(uint32_t c) { return (uint16_t)((c << 5) + 0x3c00u); }
+
 // Column offsets R_j - 2 rlo and the mask of fractions some searched stage needs.
 template <int NH>
 __device__ __forceinline__ uint32_t column_offsets(int64_t R, int64_t rlo, int64_t *col) {
@@ -175,20 +211,24 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
 // rows a block's sums read, frac_row(zq, j) for zq in the block, lie in row
 // blocks a..e (a host table, packed as a | (e - a) << 24, read through scalar
 // loads since every index is wave-uniform); the largest block maximum among
-// them (maxima cover both half-bin columns of a bin with pairing; stored as
-// halves rounded up) bounds every value the fraction contributes. The stage chain of these bounds (same order
-// as the exact chain) bounds every exact stage sum of the block, so a block
+// them bounds every value the fraction contributes. Maxima per bin cover both
+// half-bin columns of a bin as halves rounded up; maxima per column are 8-bit
+// codes rounded up (bound_code), the codes of blocks k and k + 1 in one
+// 16-bit word, so one gather covers a range of one or two blocks. The stage
+// chain of these bounds (same order as the exact chain, each step rounding
+// like an FP32 addition) bounds every exact stage sum of the block, so a block
 // whose bounds stay at or below all searched stages' thresholds cannot hold a
 // candidate and is skipped. A block that some lane of the wave cannot rule out
 // is summed exactly by the whole wave.
 //
 // A range spans one or two row blocks in all but rare cases: the loads of
-// the first and second block of every fraction are independent and in flight
-// together, and only longer ranges take a further loop. Block-maxima addresses are a uniform per-series base
-// plus a 32-bit byte offset per lane (one series' maxima stay below 4 GiB).
-// Maxima are gathered as halves (half the bytes and cache lines).
-// The kernel is bound by the latency of these gathers, so occupancy matters
-// more than sharing the block bookkeeping between many series per lane.
+// the first and second block of every fraction (maxima per bin) or the one
+// code pair (per column) are independent and in flight together, and only
+// longer ranges take a further loop. Block-maxima addresses are a uniform
+// per-series base plus a 32-bit byte offset per lane (one series' maxima stay
+// below 4 GiB). The kernel is bound by the issue of these gathers (about seven
+// texture-addresser cycles per 64-lane gather of one cache line), so what
+// counts is gathers times lines: 16-bit entries, one per column.
 
 template <int NH>
 struct BoundCfg {
@@ -204,15 +244,17 @@ __device__ __forceinline__ uint16_t load_bits_at(const bmax_t *base, uint32_t by
 }
 
 // Tile g of one set of series: series group g / tiles_per_series (SB series),
-// 256 columns from (g mod tiles_per_series) * 256.
-template <int NH>
+// 256 columns from (g mod tiles_per_series) * 256. PW: block maxima per column
+// as 32-bit pair words (the halves of blocks k and k + 1); otherwise one half
+// per bin (both half-bin columns).
+template <int NH, bool PW>
 __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane, int64_t pitch,
                                                 int64_t sstride, const bmax_t *__restrict__ pyr,
                                                 int64_t psstride, const int32_t *__restrict__ blk_lo,
                                                 const int32_t *__restrict__ frange, int nblk, int64_t NR,
                                                 int64_t rlo, int Z, const float *__restrict__ thr,
                                                 float *__restrict__ maxv, int16_t *__restrict__ zarg,
-                                                int64_t mpitch, int64_t tiles_per_series, int64_t g, int pair,
+                                                int64_t mpitch, int64_t tiles_per_series, int64_t g,
                                                 int64_t ppitch, int nseries) {
     constexpr int NS = Stages<NH>::NS;
     constexpr int SB = BoundCfg<NH>::SB;
@@ -245,22 +287,33 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
 #pragma unroll
         for (int j = 0; j < NH; ++j) {
             const int64_t cc = col[j] < 0 ? 0 : col[j];
-            cb[j] = (uint32_t)(pair ? cc >> 1 : cc) * (uint32_t)sizeof(bmax_t);
+            cb[j] = (uint32_t)(PW ? cc : cc >> 1) * (uint32_t)sizeof(bmax_t);
         }
     }
+    // each series' block maxima (below 4 GiB): a pointer (halves per bin) or a
+    // buffer resource (code pairs per column)
     const bmax_t *yb[SB];
+    __amdgpu_buffer_rsrc_t rs[SB];
 #pragma unroll
     for (int m = 0; m < SB; ++m) {
         const int bm = b0 + m < nseries ? b0 + m : nseries - 1;   // spare lanes re-read the last series
         yb[m] = pyr + (int64_t)bm * psstride;
+        rs[m] = __builtin_amdgcn_make_buffer_rsrc(const_cast<bmax_t *>(yb[m]), (short)0,
+                                                  (int)(uint32_t)(psstride * (int64_t)sizeof(bmax_t)),
+                                                  kBufferRsrcWord3);
     }
     const uint32_t rowb = (uint32_t)ppitch * (uint32_t)sizeof(bmax_t);   // bytes per row block
+    const int32_t *boff = frange + nblk * NH;   // gather offsets of the bound tests
     float th[NS];
     bool valid[NS];
+    // code pairs saturate at kCodeMax: a threshold at or above it could not be
+    // told from a saturated bound, so every block is then summed exactly
+    bool all_hot = false;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         th[s] = thr[s];
         valid[s] = R >= 2 * rlo * (1 << s);
+        if (PW) all_hot |= !(th[s] < kCodeMax);
     }
     // Exact maxima over the hot blocks and their smallest maximising Zq: a
     // column's maximum above threshold lies in a hot block (every other block's
@@ -278,80 +331,136 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
 #pragma unroll
         for (int h = 0; h < NP; ++h) azp[m][h] = 0u;
     }
-    for (int k0 = 0; k0 < nblk; k0 += 64) {
+    for (int k0 = 0; k0 < nblk; k0 += kBoundChunk) {
         // pass 1: per series, a wave-uniform mask of the blocks some lane cannot rule out
         uint64_t hotmask[SB];
 #pragma unroll
         for (int m = 0; m < SB; ++m) hotmask[m] = 0;
-        const int kend = nblk - k0 < 64 ? nblk - k0 : 64;
+        const int kend = nblk - k0 < kBoundChunk ? nblk - k0 : kBoundChunk;
         for (int kk = 0; kk < kend; ++kk) {
-            const int32_t *fr = frange + (k0 + kk) * NH;
-            // The first row block of every range, and the second only where
-            // the range has one (a wave-uniform test; about a third of the
-            // ranges at 6-row blocks and 16 harmonics). The block's ranges are
-            // read before the first test: inside the tests each would be a
-            // scalar load of its own that the next gathers wait for. The
-            // gathers keep their raw half bits, so no conversion sits in a
-            // branch where it would wait for all earlier loads, and both
-            // blocks' bits merge by an integer maximum (non-negative halves
-            // order like their bits).
-            float B[SB][NH];
-            int wide = 0;
-            {
-                int32_t fv[NH];
+            if constexpr (PW) {
+                // Code pairs per column: one gather per fraction and block,
+                // none under a branch, through buffer resources with the row
+                // block's byte offset from a host table as the scalar offset
+                // and the lane's column as the vector offset (no lane computes
+                // an address): o[j] is the byte offset of the code pair of row
+                // block a; o[NH + j] the byte selector that keeps block a + 1's
+                // code where the range has it and zeroes it otherwise. Codes
+                // order like their values, so a range's bound is the larger
+                // code. Fractions that no searched stage of this lane needs are
+                // gathered and summed like the others: they only enter the sums
+                // of stages the lane does not search.
+                const int32_t *bt = boff + (k0 + kk) * (2 * NH + 2);
+                int32_t o[2 * NH + 2];
 #pragma unroll
-                for (int j = 0; j < NH; ++j) fv[j] = fr[j];
-                uint16_t Bb[SB][NH], Cb[SB][NH];
-                // a zero the compiler cannot see through: with a literal 0 it
-                // folds the merge into the branch, where it waits for every
-                // earlier gather
-                const uint16_t zero = (uint16_t)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+                for (int i = 0; i < 2 * NH + 2; ++i) o[i] = bt[i];
+                uint16_t B[SB][NH];   // half bits of the fractions' bounds
+                uint32_t w[SB][NH];
 #pragma unroll
                 for (int j = 0; j < NH; ++j) {
-                    const int32_t f = fv[j];
-                    const int n = f >> 24;
-                    wide |= n > 1;
-                    const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
 #pragma unroll
-                    for (int m = 0; m < SB; ++m) {
-                        Bb[m][j] = load_bits_at(yb[m], o0);
-                        Cb[m][j] = zero;
-                    }
-                    if (n > 0) {
-#pragma unroll
-                        for (int m = 0; m < SB; ++m) Cb[m][j] = load_bits_at(yb[m], o0 + rowb);
-                    }
+                    for (int m = 0; m < SB; ++m) w[m][j] = __builtin_amdgcn_raw_buffer_load_b16(rs[m], cb[j], o[j], 0);
                 }
 #pragma unroll
                 for (int m = 0; m < SB; ++m) {
 #pragma unroll
-                    for (int j = 0; j < NH; ++j)
-                        B[m][j] = half_bits_to_float(Bb[m][j] > Cb[m][j] ? Bb[m][j] : Cb[m][j]);
+                    for (int j = 0; j < NH; ++j) B[m][j] = code_half_bits(max_code(w[m][j], (uint32_t)o[NH + j]));
                 }
-            }
-            if (wide) {
-                // ranges over three or more row blocks (wave-uniform, rare)
+                if (o[2 * NH + 1]) {
+                    // ranges over three or more row blocks (wave-uniform, rare):
+                    // blocks a + 2 .. e, the low code of their pairs
+                    const int32_t *fr = frange + (k0 + kk) * NH;
 #pragma unroll
-                for (int j = 0; j < NH; ++j) {
-                    const int32_t f = fr[j];
-                    const int n = f >> 24;
-                    for (int k = 2; k <= n; ++k) {
-                        const uint32_t o = (uint32_t)((f & 0xffffff) + k) * rowb + cb[j];
+                    for (int j = 0; j < NH; ++j) {
+                        const int n = fr[j] >> 24;
+                        for (int k = 2; k <= n; ++k) {
+                            const int32_t off = o[j] + k * (int32_t)rowb;
 #pragma unroll
-                        for (int m = 0; m < SB; ++m) B[m][j] = fmaxf(B[m][j], load_at(yb[m], o));
+                            for (int m = 0; m < SB; ++m) {
+                                const uint16_t v = code_half_bits(__builtin_amdgcn_raw_buffer_load_b16(rs[m], cb[j], off, 0) & 0xffu);
+                                B[m][j] = B[m][j] > v ? B[m][j] : v;
+                            }
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int m = 0; m < SB; ++m) {
+                for (int m = 0; m < SB; ++m) {
+                    float U[NS];
+                    stage_chain_h<NH>(B[m], U);
+                    bool hot = false;
 #pragma unroll
-                for (int j = 0; j < NH; ++j) B[m][j] = ((need >> j) & 1u) ? B[m][j] : 0.0f;
-                float U[NS];
-                stage_chain<NH>(B[m], U);
-                bool hot = false;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) hot |= valid[s] && (U[s] > th[s]);
-                if (__any(hot)) hotmask[m] |= 1ull << kk;
+                    for (int s = 0; s < NS; ++s) hot |= valid[s] && (U[s] > th[s]);
+                    if (__any(hot) || all_hot) hotmask[m] |= 1ull << kk;
+                }
+            } else {
+                const int32_t *fr = frange + (k0 + kk) * NH;
+                // The first row block of every range, and the second only where
+                // the range has one (a wave-uniform test; about a third of the
+                // ranges at 6-row blocks and 16 harmonics). The block's ranges are
+                // read before the first test: inside the tests each would be a
+                // scalar load of its own that the next gathers wait for. The
+                // gathers keep their raw half bits, so no conversion sits in a
+                // branch where it would wait for all earlier loads, and both
+                // blocks' bits merge by an integer maximum (non-negative halves
+                // order like their bits).
+                float B[SB][NH];
+                int wide = 0;
+                {
+                    int32_t fv[NH];
+    #pragma unroll
+                    for (int j = 0; j < NH; ++j) fv[j] = fr[j];
+                    uint16_t Bb[SB][NH], Cb[SB][NH];
+                    // a zero the compiler cannot see through: with a literal 0 it
+                    // folds the merge into the branch, where it waits for every
+                    // earlier gather
+                    const uint16_t zero = (uint16_t)__builtin_amdgcn_mbcnt_lo(0u, 0u);
+    #pragma unroll
+                    for (int j = 0; j < NH; ++j) {
+                        const int32_t f = fv[j];
+                        const int n = f >> 24;
+                        wide |= n > 1;
+                        const uint32_t o0 = (uint32_t)(f & 0xffffff) * rowb + cb[j];
+    #pragma unroll
+                        for (int m = 0; m < SB; ++m) {
+                            Bb[m][j] = load_bits_at(yb[m], o0);
+                            Cb[m][j] = zero;
+                        }
+                        if (n > 0) {
+    #pragma unroll
+                            for (int m = 0; m < SB; ++m) Cb[m][j] = load_bits_at(yb[m], o0 + rowb);
+                        }
+                    }
+    #pragma unroll
+                    for (int m = 0; m < SB; ++m) {
+    #pragma unroll
+                        for (int j = 0; j < NH; ++j)
+                            B[m][j] = half_bits_to_float(Bb[m][j] > Cb[m][j] ? Bb[m][j] : Cb[m][j]);
+                    }
+                }
+                if (wide) {
+                    // ranges over three or more row blocks (wave-uniform, rare)
+    #pragma unroll
+                    for (int j = 0; j < NH; ++j) {
+                        const int32_t f = fr[j];
+                        const int n = f >> 24;
+                        for (int k = 2; k <= n; ++k) {
+                            const uint32_t o = (uint32_t)((f & 0xffffff) + k) * rowb + cb[j];
+    #pragma unroll
+                            for (int m = 0; m < SB; ++m) B[m][j] = fmaxf(B[m][j], load_at(yb[m], o));
+                        }
+                    }
+                }
+    #pragma unroll
+                for (int m = 0; m < SB; ++m) {
+    #pragma unroll
+                    for (int j = 0; j < NH; ++j) B[m][j] = ((need >> j) & 1u) ? B[m][j] : 0.0f;
+                    float U[NS];
+                    stage_chain<NH>(B[m], U);
+                    bool hot = false;
+    #pragma unroll
+                    for (int s = 0; s < NS; ++s) hot |= valid[s] && (U[s] > th[s]);
+                    if (__any(hot)) hotmask[m] |= 1ull << kk;
+                }
             }
         }
         // pass 2: exact sums of the hot blocks
@@ -424,7 +533,7 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
     }
 }
 
-template <int NH>
+template <int NH, bool PW>
 __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ plane, int64_t pitch,
                                                     int64_t sstride, const bmax_t *__restrict__ pyr,
                                                     int64_t psstride, const int32_t *__restrict__ blk_lo,
@@ -433,7 +542,7 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
                                                     const float *__restrict__ thr,
                                                     float *__restrict__ maxv, int16_t *__restrict__ zarg,
                                                     int64_t mpitch, int64_t tiles_per_series,
-                                                    int64_t total_tiles, int pair, int64_t ppitch, int nseries) {
+                                                    int64_t total_tiles, int64_t ppitch, int nseries) {
     // each XCD (workgroup id mod 8) takes a contiguous run of (series group,
     // column tile) items: neighbouring tiles read overlapping fraction strips
     // through its L2
@@ -441,8 +550,8 @@ __global__ __launch_bounds__(256) void k_harm_bound(const float *__restrict__ pl
     const int64_t per_xcd = (total_tiles + 7) / 8;
     const int64_t g = (w & 7) * per_xcd + (w >> 3);
     if (g >= total_tiles) return;
-    harm_bound_tile<NH>(plane, pitch, sstride, pyr, psstride, blk_lo, frange, nblk, NR, rlo, Z, thr, maxv, zarg,
-                        mpitch, tiles_per_series, g, pair, ppitch, nseries);
+    harm_bound_tile<NH, PW>(plane, pitch, sstride, pyr, psstride, blk_lo, frange, nblk, NR, rlo, Z, thr, maxv,
+                            zarg, mpitch, tiles_per_series, g, ppitch, nseries);
 }
 
 // A pointer read from memory is generic for the compiler (flat loads with
@@ -475,16 +584,32 @@ __global__ __launch_bounds__(256) void k_harm_bound_list(const HarmItem *__restr
     const int64_t run = starts[lo + 1] - starts[lo];
     const int64_t g = (w & 7) * run + (l - starts[lo]);
     if (g >= it.ntiles) return;
-    harm_bound_tile<NH>(global_ptr(it.plane), it.pitch, it.sstride, global_ptr(it.pyr), it.psstride,
-                        global_ptr(it.blk_lo), global_ptr(it.frange), it.nblk, it.NR, it.rlo, it.Z, thr,
-                        global_ptr(it.maxv), global_ptr(it.zarg), it.mpitch, it.tiles_per_series, g, it.pair,
-                        it.ppitch, it.nseries);
+    if (it.pair)
+        harm_bound_tile<NH, false>(global_ptr(it.plane), it.pitch, it.sstride, global_ptr(it.pyr), it.psstride,
+                                   global_ptr(it.blk_lo), global_ptr(it.frange), it.nblk, it.NR, it.rlo, it.Z,
+                                   thr, global_ptr(it.maxv), global_ptr(it.zarg), it.mpitch, it.tiles_per_series,
+                                   g, it.ppitch, it.nseries);
+    else
+        harm_bound_tile<NH, true>(global_ptr(it.plane), it.pitch, it.sstride, global_ptr(it.pyr), it.psstride,
+                                  global_ptr(it.blk_lo), global_ptr(it.frange), it.nblk, it.NR, it.rlo, it.Z,
+                                  thr, global_ptr(it.maxv), global_ptr(it.zarg), it.mpitch, it.tiles_per_series,
+                                  g, it.ppitch, it.nseries);
 }
 
 // Block maxima of a caller-supplied plane (what K4 writes while it builds the
-// plane): per column, pyr[b][k][c] = max over the rows of block k of
-// plane[b][row][c]; with pair, pyr[b][k][i] covers columns 2i and 2i+1.
-// Stored rounded up to half precision, like K4's.
+// plane). With pair, pyr[b][k][i] covers columns 2i and 2i+1 as a half rounded
+// up; otherwise column c of row block k holds the 16-bit word of the
+// bound_code()s of the maxima of blocks k (low byte) and k + 1 (high byte, 0
+// above the last block).
+__device__ __forceinline__ float block_max_of(const float *src, int64_t pitch, int r0, int r1, int pair) {
+    float mx = 0.0f;
+    for (int r = r0; r < r1; ++r) {
+        const float *q = src + (int64_t)r * pitch;
+        mx = fmaxf(mx, pair ? fmaxf(q[0], q[1]) : q[0]);
+    }
+    return mx;
+}
+
 __global__ __launch_bounds__(256) void k_block_max(const float *__restrict__ plane, int64_t pitch,
                                                    int64_t sstride, int64_t NR,
                                                    const int32_t *__restrict__ blk_lo, int nblk,
@@ -495,12 +620,14 @@ __global__ __launch_bounds__(256) void k_block_max(const float *__restrict__ pla
     const int64_t ncol = pair ? NR / 2 : NR;
     if (i >= ncol || k >= nblk) return;
     const float *src = plane + (int64_t)b * sstride + (pair ? 2 * i : i);
-    float mx = 0.0f;
-    for (int r = blk_lo[k]; r < blk_lo[k + 1]; ++r) {
-        const float *q = src + (int64_t)r * pitch;
-        mx = fmaxf(mx, pair ? fmaxf(q[0], q[1]) : q[0]);
+    const float mk = block_max_of(src, pitch, blk_lo[k], blk_lo[k + 1], pair);
+    bmax_t *row = pyr + (int64_t)b * psstride + (int64_t)k * ppitch;
+    if (pair) {
+        row[i] = bound_half(mk);
+    } else {
+        const uint32_t c1 = k + 1 < nblk ? bound_code(block_max_of(src, pitch, blk_lo[k + 1], blk_lo[k + 2], 0)) : 0u;
+        row[i] = (bmax_t)(bound_code(mk) | (c1 << 8));
     }
-    pyr[(int64_t)b * psstride + (int64_t)k * ppitch + i] = bound_half(mx);
 }
 
 hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_stride, int64_t NR,
@@ -508,7 +635,8 @@ hipError_t launch_block_max(const float *plane, int64_t pitch, int64_t series_st
                             hipStream_t st) {
     const int64_t ncol = rb.pair ? NR / 2 : NR;
     if (nseries < 1 || nseries > 65535 || rb.nblk < 1 || rb.nblk > 65535 || !rb.lo || (pitch & 1) ||
-        (NR & 1) || rb.ppitch < ncol || (rb.ppitch & 31) || pyr_series_stride < rb.nblk * rb.ppitch)
+        (NR & 1) || rb.ppitch < ncol || (rb.ppitch & 31) ||
+        pyr_series_stride < rb.nblk * rb.ppitch)
         return hipErrorInvalidValue;
     dim3 grid((unsigned)((ncol + 255) / 256), (unsigned)rb.nblk, (unsigned)nseries);
     hipLaunchKernelGGL(k_block_max, grid, dim3(256), 0, st, plane, pitch, series_stride, NR, rb.lo,
@@ -552,6 +680,9 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ maxv,
                                                  const int64_t *__restrict__ offsets,
                                                  DevCand *__restrict__ out, int64_t cap) {
     __shared__ int tmp[4];
+    // the scatter pass skips the blocks the counting pass found empty (most of
+    // them: candidates are rare), without reading their maxima
+    if (SCATTER && counts[blockIdx.x] == 0) return;
     const int64_t e0 = (int64_t)blockIdx.x * kCB + (int64_t)threadIdx.x * 16;
     float v[16];
     int row = 0;
@@ -706,9 +837,14 @@ static void launch_bound_nh(const float *plane, int64_t pitch, int64_t sstride, 
     const int64_t groups = (nseries + BoundCfg<NH>::SB - 1) / BoundCfg<NH>::SB;
     const int64_t total = tps * groups;
     const int64_t nwg = 8 * ((total + 7) / 8);
-    hipLaunchKernelGGL(k_harm_bound<NH>, dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch, sstride,
-                       pyr, psstride, rb.lo, rb.frange, rb.nblk, NR, rlo, Z, thr, maxv, zarg, mpitch, tps,
-                       total, rb.pair ? 1 : 0, rb.ppitch, nseries);
+    if (rb.pair)
+        hipLaunchKernelGGL((k_harm_bound<NH, false>), dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch,
+                           sstride, pyr, psstride, rb.lo, rb.frange, rb.nblk, NR, rlo, Z, thr, maxv, zarg, mpitch,
+                           tps, total, rb.ppitch, nseries);
+    else
+        hipLaunchKernelGGL((k_harm_bound<NH, true>), dim3((unsigned)nwg), dim3(256), 0, st, plane, pitch,
+                           sstride, pyr, psstride, rb.lo, rb.frange, rb.nblk, NR, rlo, Z, thr, maxv, zarg, mpitch,
+                           tps, total, rb.ppitch, nseries);
 }
 
 hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t series_stride,
@@ -720,7 +856,7 @@ hipError_t launch_harmsum_bounded(const float *plane, int64_t pitch, int64_t ser
     if (nseries < 1 || mpitch < NR || (mpitch & 15) || (mpitch + 255) / 256 * nseries > 0x7ffffff0LL ||
         !pyr || !rb.lo || !rb.frange || rb.nblk < 1 || rb.frange_nh != numharm ||
         bounded_table_bytes(rb.nblk, numharm) > kBoundTableMax || pyr_series_stride > kMaxPyrSeriesStride ||
-        !zarg || Z > 32767 || (rb.ppitch & 31) || rb.ppitch < (rb.pair ? NR / 2 : NR) ||
+        !zarg || Z > 32767 || (rb.ppitch & 31) || rb.ppitch < (rb.pair ? NR / 2 : NR) || rb.table_ppitch != rb.ppitch ||
         pyr_series_stride < rb.nblk * rb.ppitch)
         return hipErrorInvalidValue;
 #define FDAS_BOUND(NHV) launch_bound_nh<NHV>(plane, pitch, series_stride, pyr, pyr_series_stride, rb, NR, rlo, Z, nseries, thr_dev, maxv, zarg, mpitch, st)

@@ -416,3 +416,23 @@ def test_bounded_search_exact_with_powers_beyond_the_largest_half(fdas_gpu):
     got = plan.search(x, ts, sigma=6.0, cap=1 << 18)
     assert len(ref) > 5
     assert np.array_equal(ref, got)
+
+
+def test_bounded_search_exact_when_thresholds_pass_the_code_range(fdas_gpu):
+    """Per-column block maxima are 8-bit codes that saturate at 252: with a
+    stage threshold at or above that (high sigma) a saturated bound could not
+    be told from a candidate, so every block is summed exactly; the records
+    still equal those of the exhaustive sums."""
+    B, N, ts, zmax, dz, nh, sigma = 2, 1 << 14, 1e-3, 40.0, 2.0, 16, 20.0
+    assert fdas_gpu.threshold(16, sigma) >= 252.0 > fdas_gpu.threshold(8, sigma)
+    rng = np.random.default_rng(99)
+    t = np.arange(N) * ts
+    T = N * ts
+    x = rng.standard_normal((B, N))
+    for b, (f, z, amp) in enumerate([(61.9, 8.0, 60.0), (143.21, -24.0, 45.0)]):
+        x[b] += amp * np.cos(2 * np.pi * (f * t + 0.5 * z / T ** 2 * t ** 2))
+    x = _cuda(x.astype(np.float32))
+    ref = fdas_gpu.Plan(N, B, zmax, dz, nh, harm_bound=1).search(x, ts, sigma=sigma, cap=1 << 18)
+    got = fdas_gpu.Plan(N, B, zmax, dz, nh, harm_pair=1).search(x, ts, sigma=sigma, cap=1 << 18)
+    assert len(ref) > 5
+    assert np.array_equal(ref, got)
