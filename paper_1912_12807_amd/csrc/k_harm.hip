@@ -219,7 +219,8 @@ __global__ __launch_bounds__(256) void k_harmsum(const float *__restrict__ plane
 // like an FP32 addition) bounds every exact stage sum of the block, so a block
 // whose bounds stay at or below all searched stages' thresholds cannot hold a
 // candidate and is skipped. A block that some lane of the wave cannot rule out
-// is summed exactly by the whole wave.
+// is summed exactly by those lanes (the others masked off), with the row
+// bookkeeping shared by the wave.
 //
 // A range spans one or two row blocks in all but rare cases: the loads of
 // the first and second block of every fraction (maxima per bin) or the one
@@ -315,11 +316,12 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
         valid[s] = R >= 2 * rlo * (1 << s);
         if (PW) all_hot |= !(th[s] < kCodeMax);
     }
-    // Exact maxima over the hot blocks and their smallest maximising Zq: a
-    // column's maximum above threshold lies in a hot block (every other block's
-    // sums are at or below its bound, itself at or below the threshold), and
-    // hot blocks are summed in increasing Zq with strictly larger values only
-    // replacing the maximum. The Zq of two stages share a register as 16-bit
+    // Exact maxima over the column's hot blocks and their smallest maximising
+    // Zq: a column's maximum above threshold lies in a block that is hot for
+    // that column (every other block's sums are at or below its bound, itself
+    // at or below the threshold), and hot blocks are summed in increasing Zq
+    // with strictly larger values only replacing the maximum. Stage maxima at
+    // or below the threshold are not candidates, whatever blocks they cover. The Zq of two stages share a register as 16-bit
     // halves (the block tests need the registers).
     constexpr int NP = (NS + 1) / 2;
     float mx[SB][NS];
@@ -333,9 +335,11 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
     }
     for (int k0 = 0; k0 < nblk; k0 += kBoundChunk) {
         // pass 1: per series, a wave-uniform mask of the blocks some lane cannot rule out
-        uint64_t hotmask[SB];
+        // per series, a wave-uniform mask of the blocks some lane cannot rule
+        // out, and each lane's own mask of the blocks it cannot rule out
+        uint64_t hotmask[SB], lanehot[SB];
 #pragma unroll
-        for (int m = 0; m < SB; ++m) hotmask[m] = 0;
+        for (int m = 0; m < SB; ++m) hotmask[m] = lanehot[m] = 0;
         const int kend = nblk - k0 < kBoundChunk ? nblk - k0 : kBoundChunk;
         for (int kk = 0; kk < kend; ++kk) {
             if constexpr (PW) {
@@ -390,7 +394,9 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
                     bool hot = false;
 #pragma unroll
                     for (int s = 0; s < NS; ++s) hot |= valid[s] && (U[s] > th[s]);
-                    if (__any(hot) || all_hot) hotmask[m] |= 1ull << kk;
+                    hot |= all_hot;
+                    if (hot) lanehot[m] |= 1ull << kk;
+                    if (__any(hot)) hotmask[m] |= 1ull << kk;
                 }
             } else {
                 const int32_t *fr = frange + (k0 + kk) * NH;
@@ -459,6 +465,7 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
                     bool hot = false;
     #pragma unroll
                     for (int s = 0; s < NS; ++s) hot |= valid[s] && (U[s] > th[s]);
+                    if (hot) lanehot[m] |= 1ull << kk;
                     if (__any(hot)) hotmask[m] |= 1ull << kk;
                 }
             }
@@ -476,8 +483,12 @@ __device__ __forceinline__ void harm_bound_tile(const float *__restrict__ plane,
             const float *pb = plane + (int64_t)(b0 + m) * sstride;
             uint64_t hm = hotmask[m];
             while (hm) {
-                const int kb = k0 + __builtin_ctzll(hm);
+                const int kk = __builtin_ctzll(hm), kb = k0 + kk;
                 hm &= hm - 1;
+                // only the lanes whose own bound is hot sum the block: a lane
+                // whose bounds stay at or below every threshold holds no
+                // candidate in it, and its maxima matter only above them
+                if (!((lanehot[m] >> kk) & 1u)) continue;
                 const int zqa = blk_lo[kb] - Z, zqb = blk_lo[kb + 1] - 1 - Z;
                 // as the exhaustive sweep: fraction values stay in registers and
                 // are reloaded only when their (wave-uniform) row changes, the
