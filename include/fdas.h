@@ -320,8 +320,10 @@ fdas_status fdas_template_taps(double z, int32_t parity, int32_t K, double *re, 
                                int32_t cap, int32_t *ntaps, int32_t *d0);
 
 /* What a plan chose for its current template bank: overlap-save segment
- * length and shared half-width (each segment yields seg_len - 2 mseg valid
- * bins), z rows, series per plane chunk, the plane workspace in bytes, and,
+ * length and the largest template half-width (the z rows are split into
+ * groups, each segmenting the spectrum by its own widest template: a group
+ * yields seg_len - 2 m valid bins per segment, m <= mseg), z rows, series per
+ * plane chunk, the plane workspace in bytes, and,
  * for the last search, the number of drift blocks of the bounded harmonic
  * sums (0 if they were not used) and whether their maxima cover bin pairs. */
 typedef struct {

@@ -133,12 +133,16 @@ struct LaunchCfg {
 struct Bank {
     double zmax = -1, dz = -1;
     int K = 0, L = 0, mseg = 0, NZ = 0;
+    int G = 1;                                       // z groups of K4
+    int32_t zb[kMaxZGroups + 1] = {};                // their row boundaries
+    int gmseg[kMaxZGroups] = {};                     // and template half-widths
     float2 *d = nullptr;
     uint64_t used = 0;
 };
 
 struct RowTable {
     int NZ = -1, G = -1, bz = -1, nh = -1;
+    int32_t zb[kMaxZGroups + 1] = {};
     int64_t ppitch = -1;
     int32_t *d = nullptr;
     int nblk = 0;
@@ -400,12 +404,23 @@ fdas_status get_bank(fdas_plan p, double zmax, double dz, int L, const Bank **ou
     const int NZ = 2 * Z + 1;
     const int mseg = half_width(Z * dz, K);
     if (!seg_len_ok(L, mseg)) return p->fail(FDAS_E_UNSUPPORTED, "segment length too short for zmax");
+    // each z group of K4 segments the spectrum by its own widest template, so
+    // the kernel spectra of a row place the template at its group's half-width
+    const int G = zgroups_of(NZ);
+    int32_t zb[kMaxZGroups + 1];
+    zgroup_bounds(NZ, dz, K, L, G, zb);
+    int gm[kMaxZGroups];
+    for (int i = 0; i < G; ++i)
+        gm[i] = half_width(std::max(std::abs(zb[i] - Z), std::abs(zb[i + 1] - 1 - Z)) * dz, K);
+    std::vector<int> msrow(NZ);
+    for (int i = 0; i < G; ++i)
+        for (int r = zb[i]; r < zb[i + 1]; ++r) msrow[r] = gm[i];
     std::vector<float> host((size_t)NZ * 2 * L * 2);
     const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     const bool built = run_parallel(nth, [&](int w) {
         for (int row = w; row < 2 * NZ; row += nth) {
             const int zi = row / 2, par = row % 2;
-            kernel_spectrum((zi - Z) * dz, par, K, L, mseg, host.data() + (size_t)row * L * 2);
+            kernel_spectrum((zi - Z) * dz, par, K, L, msrow[zi], host.data() + (size_t)row * L * 2);
         }
     });
     if (!built) return p->fail(FDAS_E_NOMEM, "template bank: host computation failed");
@@ -417,6 +432,9 @@ fdas_status get_bank(fdas_plan p, double zmax, double dz, int L, const Bank **ou
     b.L = L;
     b.mseg = mseg;
     b.NZ = NZ;
+    b.G = G;
+    for (int i = 0; i <= G; ++i) b.zb[i] = zb[i];
+    for (int i = 0; i < G; ++i) b.gmseg[i] = gm[i];
     TRY(dalloc(p, &b.d, (int64_t)(host.size() / 2), "template bank"));
     if (hipMemcpy(b.d, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
         const hipError_t e = hipGetLastError();
@@ -433,13 +451,16 @@ fdas_status get_bank(fdas_plan p, double zmax, double dz, int L, const Bank **ou
 // maxima pitch: lo[nblk + 1], of_row[NZ], frange[nblk][numharm] and the bound
 // test's gather table for code pairs [nblk][2 numharm + 2] in one device
 // buffer.
-fdas_status get_rows(fdas_plan p, int NZ, int G, int bz, int numharm, bool pair, int64_t ppitch, RowBlocks &rb) {
+fdas_status get_rows(fdas_plan p, int NZ, int G, const int32_t *zb, int bz, int numharm, bool pair,
+                     int64_t ppitch, RowBlocks &rb) {
     RowTable *t = nullptr;
     for (auto &x : p->tables)
-        if (x.NZ == NZ && x.G == G && x.bz == bz && x.nh == numharm && x.ppitch == ppitch) t = &x;
+        if (x.NZ == NZ && x.G == G && std::equal(zb, zb + G + 1, x.zb) && x.bz == bz && x.nh == numharm &&
+            x.ppitch == ppitch)
+            t = &x;
     if (!t) {
         std::vector<int32_t> lo, of_row, fr, bo;
-        row_blocks(NZ, G, bz, lo, of_row);
+        row_blocks(zb, G, bz, lo, of_row);
         fraction_ranges(NZ, numharm, lo, of_row, fr);
         bound_offsets(numharm, fr, ppitch, bo);
         std::vector<int32_t> all(lo);
@@ -450,6 +471,7 @@ fdas_status get_rows(fdas_plan p, int NZ, int G, int bz, int numharm, bool pair,
         RowTable n;
         n.NZ = NZ;
         n.G = G;
+        std::copy(zb, zb + G + 1, n.zb);
         n.bz = bz;
         n.nh = numharm;
         n.ppitch = ppitch;
@@ -484,15 +506,19 @@ LaunchCfg default_cfg(fdas_plan p, int Z, double dz, int numharm) {
 }
 
 CorrGeom corr_geom(const Bank &bk, const Geometry &g) {
-    CorrGeom c;
+    CorrGeom c{};
     c.L = bk.L;
     c.mseg = bk.mseg;
-    c.Lv = bk.L - 2 * bk.mseg;
     c.half = g.half;
     c.rlo = g.rlo;
-    c.nseg = (int)((g.half - g.rlo + c.Lv - 1) / c.Lv);
     c.NZ = g.NZ;
-    c.zgroups = zgroups_of(g.NZ);
+    c.zgroups = bk.G;
+    for (int i = 0; i <= bk.G; ++i) c.zb[i] = bk.zb[i];
+    for (int i = 0; i < bk.G; ++i) {
+        c.gmseg[i] = bk.gmseg[i];
+        c.gLv[i] = bk.L - 2 * bk.gmseg[i];
+        c.gnseg[i] = (int)((g.half - g.rlo + c.gLv[i] - 1) / c.gLv[i]);
+    }
     return c;
 }
 
@@ -581,8 +607,8 @@ fdas_status group_item(fdas_plan p, const Geometry &g, const Bank &bk, const Lau
     it.vbase = vbase;
     it.pitch = round_up(g.NR, 64);
     it.sstride = (int64_t)g.NZ * it.pitch;
-    TRY(get_rows(p, g.NZ, it.cg.zgroups, cfg.bz, numharm, cfg.pair != 0, cfg.pair ? it.pitch / 2 : it.pitch,
-                 it.rb));
+    TRY(get_rows(p, g.NZ, it.cg.zgroups, it.cg.zb, cfg.bz, numharm, cfg.pair != 0,
+                 cfg.pair ? it.pitch / 2 : it.pitch, it.rb));
     it.psstride = (int64_t)it.rb.nblk * it.rb.ppitch;
     // K4 writes the block maxima whenever the buffer sized at plan creation
     // holds those of a chunk series. The exhaustive sums do not read them, but
@@ -1667,8 +1693,9 @@ fdas_status fdas_harmsum(fdas_plan p, const float *plane_dev, int64_t nsamp, int
     RowBlocks rb;
     // maxima rows padded like the search's (a multiple of 32 halves)
     const bool mpair = maxima_per_bin(p->opts.harm_pair, numharm);
-    TRY(get_rows(p, g.NZ, 1, p->opts.harm_block ? p->opts.harm_block : default_block_rows(numharm), numharm,
-                 mpair, mpair ? round_up(g.NR, 64) / 2 : round_up(g.NR, 64), rb));
+    const int32_t whole[2] = {0, g.NZ};
+    TRY(get_rows(p, g.NZ, 1, whole, p->opts.harm_block ? p->opts.harm_block : default_block_rows(numharm),
+                 numharm, mpair, mpair ? round_up(g.NR, 64) / 2 : round_up(g.NR, 64), rb));
     const int64_t psstride = (int64_t)rb.nblk * rb.ppitch;
     int64_t chunk = std::min<int64_t>(p->max_series, p->maxv_cap / (NS * mpitch));
     const bool bounded = !p->opts.harm_bound && bounded_table_bytes(rb.nblk, numharm) <= kBoundTableMax &&

@@ -99,17 +99,28 @@ hipError_t launch_local_norm(float2 *spec, int64_t spitch, int64_t half, int nse
 // scale[0..nseries) = value (the fixed-variance normalisation).
 hipError_t launch_fill_scale(float *scale, int nseries, float value, hipStream_t st);
 
-// K4: overlap-save correlation with the template bank and power.
+// K4: overlap-save correlation with the template bank and power. The z rows
+// are split into zgroups contiguous groups (one per XCD); group i covers rows
+// zb[i] .. zb[i + 1] - 1 and segments the spectrum by its own widest
+// template: half-width gmseg[i], gLv[i] = L - 2 gmseg[i] valid outputs per
+// segment, gnseg[i] segments per series.
+constexpr int kMaxZGroups = 8;
 struct CorrGeom {
     int L;            // segment length (512, 1024, 2048 or 4096)
-    int mseg;         // shared template half-width of the bank
-    int Lv;           // valid outputs per segment, L - 2 mseg
-    int nseg;         // segments per series
+    int mseg;         // largest template half-width (of the widest group)
     int64_t half;     // n/2
     int64_t rlo;      // lowest searched bin
     int NZ;           // z rows
     int zgroups;      // z rows are split in this many groups (1, 2, 4, 8)
+    int zb[kMaxZGroups + 1];
+    int gmseg[kMaxZGroups], gLv[kMaxZGroups], gnseg[kMaxZGroups];
 };
+// Row boundaries zb[0..G] of the G z groups of K4 for NZ rows at spacing dz
+// (templates of half-width half_width(z, K), segments of length L): contiguous
+// groups chosen so that the plane kernel's time is as even as possible over
+// the groups (one per XCD), a group's time being its rows divided by its
+// valid outputs per segment. Every group keeps at least one row.
+void zgroup_bounds(int NZ, double dz, int K, int L, int G, int32_t *zb);
 // Drift-row blocks for the block maxima ("pyramid"): block k covers rows
 // [lo[k], lo[k+1]); blocks never straddle a z group of K4. of_row[r] is the
 // block of row r. Both tables live in device memory.
@@ -129,9 +140,10 @@ struct RowBlocks {
     int64_t ppitch = 0;               // 16-bit entries per row block of the maxima (a multiple
                                       // of 32): pitch / 2 per bin, pitch per column
 };
-// Host construction of the row-block partition for NZ rows, G z groups and
-// blocks of at most bz rows (as even as possible inside each group).
-void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int32_t> &of_row);
+// Host construction of the row-block partition for the NZ = zb[G] rows of G z
+// groups (boundaries zb) with blocks of at most bz rows (as even as possible
+// inside each group).
+void row_blocks(const int32_t *zb, int G, int bz, std::vector<int32_t> &lo, std::vector<int32_t> &of_row);
 // Host table of the row blocks each harmonic fraction of each block reads.
 void fraction_ranges(int NZ, int numharm, const std::vector<int32_t> &lo,
                      const std::vector<int32_t> &of_row, std::vector<int32_t> &frange);

@@ -23,6 +23,9 @@
 #include "dft_small.h"
 #include "fdas_internal.h"
 
+#include <algorithm>
+#include <cstdlib>
+
 namespace fdas {
 
 template <int L>
@@ -183,11 +186,13 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
     const int per = 8 / G;
     const int zg = xcd & (G - 1);
     const int64_t unit = (int64_t)(w >> 3) * per + xcd / G;
-    if (unit >= (int64_t)nseries * g.nseg) return;
-    const int b = (int)(unit / g.nseg);
-    const int s = (int)(unit - (int64_t)b * g.nseg);
-    const int z0 = zg * g.NZ / G, z1 = (zg + 1) * g.NZ / G;
-    const int64_t ks = g.rlo + (int64_t)s * g.Lv;   // first output bin of the segment
+    // the group's own segmentation (its widest template)
+    const int nseg = g.gnseg[zg], Lv = g.gLv[zg], mseg = g.gmseg[zg];
+    if (unit >= (int64_t)nseries * nseg) return;
+    const int b = (int)(unit / nseg);
+    const int s = (int)(unit - (int64_t)b * nseg);
+    const int z0 = g.zb[zg], z1 = g.zb[zg + 1];
+    const int64_t ks = g.rlo + (int64_t)s * Lv;   // first output bin of the segment
 
     Twiddles<L> tw;
     make_twiddles<L>(tw, t);
@@ -206,7 +211,7 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
     float2 S[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const int64_t k = ks - g.mseg + t + q * T;
+        const int64_t k = ks - mseg + t + q * T;
         S[q] = (k >= 1 && k < g.half) ? A[k] : make_float2(0.0f, 0.0f);
     }
     fft_block<L, -1>(S, lds, sel, tw, a);
@@ -242,7 +247,7 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
     const int t_row = 2 * t * (int)sizeof(float);
     for (int zi = z0; zi < z1; ++zi) {
         const __amdgpu_buffer_rsrc_t row_rs = __builtin_amdgcn_make_buffer_rsrc(
-            out + (int64_t)zi * pitch, (short)0, 2 * g.Lv * (int)sizeof(float), kBufferRsrcWord3);
+            out + (int64_t)zi * pitch, (short)0, 2 * Lv * (int)sizeof(float), kBufferRsrcWord3);
         // up to L 2048 the parity-0 powers wait in registers and both
         // parities of a bin are stored as one 8-byte pair (whole lines, half
         // the store instructions); at L 4096 that would cost the registers of
@@ -266,12 +271,12 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
                 if constexpr (kPairStore) {
                     if (p == 0) {
                         pw0[q] = pw;
-                    } else if (i < g.Lv && ks + i < g.half) {
+                    } else if (i < Lv && ks + i < g.half) {
                         typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
                         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(pw0[q], pw)),
                                                               row_rs, t_row, 2 * q * T * (int)sizeof(float), 0);
                     }
-                } else if (i < g.Lv && ks + i < g.half) {
+                } else if (i < Lv && ks + i < g.half) {
                     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, pw), row_rs,
                                                           t_row + p * (int)sizeof(float),
                                                           2 * q * T * (int)sizeof(float), 0);
@@ -308,7 +313,7 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int i = t + q * T;
-                    if (i < g.Lv && ks + i < g.half) {
+                    if (i < Lv && ks + i < g.half) {
                         if constexpr (PYR == 2) {
                             prow[i] = bound_half(m0[q]);
                         } else {
@@ -368,11 +373,56 @@ __global__ __launch_bounds__(L / 8) __attribute__((amdgpu_waves_per_eu(3, 3))) v
 #undef FDAS_K4_PARAMS
 #undef FDAS_K4_ARGS
 
-void row_blocks(int NZ, int G, int bz, std::vector<int32_t> &lo, std::vector<int32_t> &of_row) {
+void zgroup_bounds(int NZ, double dz, int K, int L, int G, int32_t *zb) {
+    const int Z = (NZ - 1) / 2;
+    // valid outputs per segment of a group over rows a..e - 1 (its widest
+    // drift sets the template half-width)
+    auto valid = [&](int a, int e) {
+        const int zmax = std::max(std::abs(a - Z), std::abs(e - 1 - Z));
+        return L - 2 * half_width(zmax * dz, K);
+    };
+    // greedy cover with groups of time <= t; the smallest t that needs at most
+    // G groups (bisection over t)
+    auto cover = [&](double t, int32_t *b) {
+        int n = 0;
+        b[0] = 0;
+        while (b[n] < NZ) {
+            if (n == G) return false;
+            int e = b[n] + 1;
+            while (e < NZ && (double)(e + 1 - b[n]) / valid(b[n], e + 1) <= t) ++e;
+            b[++n] = e;
+        }
+        // fewer groups than G: split the longest until there are G
+        while (n < G) {
+            int w = 0;
+            for (int i = 1; i < n; ++i)
+                if (b[i + 1] - b[i] > b[w + 1] - b[w]) w = i;
+            for (int i = n + 1; i > w + 1; --i) b[i] = b[i - 1];
+            b[w + 1] = b[w] + (b[w + 2] - b[w]) / 2;
+            ++n;
+        }
+        return true;
+    };
+    double lo = 0.0, hi = (double)NZ;   // hi: one group per row is always feasible below this
+    int32_t b[kMaxZGroups + 2];
+    for (int i = 0; i <= G; ++i) zb[i] = i * NZ / G;
+    for (int it = 0; it < 60; ++it) {
+        const double t = 0.5 * (lo + hi);
+        if (cover(t, b)) {
+            hi = t;
+            for (int i = 0; i <= G; ++i) zb[i] = b[i];
+        } else {
+            lo = t;
+        }
+    }
+}
+
+void row_blocks(const int32_t *zb, int G, int bz, std::vector<int32_t> &lo, std::vector<int32_t> &of_row) {
+    const int NZ = zb[G];
     lo.clear();
     of_row.assign(NZ, 0);
     for (int gi = 0; gi < G; ++gi) {
-        const int z0 = gi * NZ / G, z1 = (gi + 1) * NZ / G;
+        const int z0 = zb[gi], z1 = zb[gi + 1];
         const int n = z1 - z0;
         if (n <= 0) continue;
         const int nb = (n + bz - 1) / bz;
@@ -445,13 +495,20 @@ hipError_t launch_corr_power(const float2 *spec, int64_t spitch, const float *sc
                              int64_t pitch, int64_t series_stride, bmax_t *pyr,
                              int64_t pyr_series_stride, const RowBlocks &rb, hipStream_t st) {
     // buffer resources take 32-bit byte ranges: the bank and a segment's row
-    if ((int64_t)2 * g.NZ * g.L * 8 > 0x7fffffffLL || (int64_t)2 * g.Lv * 4 > 0x7fffffffLL)
+    if ((int64_t)2 * g.NZ * g.L * 8 > 0x7fffffffLL)
         return hipErrorInvalidValue;
-    if (nseries < 1 || g.nseg < 1 || g.Lv < 1 || (g.zgroups & (g.zgroups - 1)) || g.zgroups > 8 ||
-        g.zgroups < 1 || g.zgroups > g.NZ || (pitch & 1) ||
+    if (nseries < 1 || (g.zgroups & (g.zgroups - 1)) || g.zgroups > kMaxZGroups || g.zgroups < 1 ||
+        g.zgroups > g.NZ || (pitch & 1) || g.zb[0] != 0 || g.zb[g.zgroups] != g.NZ ||
         (pyr && (!rb.lo || !rb.of_row || rb.nblk < 1 || rb.ppitch != (rb.pair ? pitch / 2 : pitch))))
         return hipErrorInvalidValue;
-    const int64_t units = (int64_t)nseries * g.nseg;
+    int maxseg = 0;
+    for (int i = 0; i < g.zgroups; ++i) {
+        if (g.zb[i + 1] <= g.zb[i] || g.gLv[i] < 1 || g.gLv[i] != g.L - 2 * g.gmseg[i] || g.gmseg[i] > g.mseg ||
+            g.gnseg[i] < 1 || (int64_t)g.gnseg[i] * g.gLv[i] < g.half - g.rlo)
+            return hipErrorInvalidValue;
+        maxseg = std::max(maxseg, g.gnseg[i]);
+    }
+    const int64_t units = (int64_t)nseries * maxseg;
     const int per = 8 / g.zgroups;
     const int64_t nwg = 8 * ((units + per - 1) / per);
     if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
