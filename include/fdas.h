@@ -360,8 +360,8 @@ fdas_status fdas_profile_read(fdas_plan p, double *ms, int64_t *launches, int32_
  * normalisation (float64 [nseries], host). It calls no allocating routine: its
  * FFT buffers, scales and median histograms live in a fixed device array of
  * FDAS_NOALLOC_SCRATCH_BYTES per GPU, kept until the process ends, so
- * 2 nseries (nsamp/2) 8 bytes plus about 8 KiB per series must fit in it
- * (e.g. 8 series of 2^20 samples); larger requests return FDAS_E_INVAL.
+ * nseries (nsamp/2) 8 bytes plus about 8 KiB per series must fit in it
+ * (e.g. 12 series of 2^20 samples); larger requests return FDAS_E_INVAL.
  * Calls on one GPU share that array: calls that overlap on one GPU (other
  * streams or host threads) race; consecutive calls are independent.
  * Errors: FDAS_E_INVAL (NULL or misaligned pointer, odd nsamp or below 8,

@@ -100,8 +100,10 @@ int zgroups_of(int NZ) {
 // Drift rows per bound block. Above 8 harmonics, longer blocks are more often
 // hot (a strong line enters many stage sums) and cost more when they are:
 // 32 x 2^23 series with mains tones at numharm 16 took 83, 66, 68 and 99 ms of
-// harmonic sums with 4, 6, 8 and 10 rows.
-int default_block_rows(int numharm) { return numharm <= 8 ? 10 : 6; }
+// harmonic sums with 4, 6, 8 and 10 rows (46 ms at 6 with the code-pair
+// bounds). Up to 8 harmonics, 128 x 2^18 series took 2.58, 2.34, 2.25, 2.43 and
+// 2.47 ms with 6 to 10 rows.
+int default_block_rows(int numharm) { return numharm <= 8 ? 8 : 6; }
 // Block maxima per bin (both half-bin columns) or per column. Per column bounds
 // are tighter at twice the memory; above 8 harmonics, where a strong line's
 // half-bin neighbours enter many more stage sums, they win (e.g. 347 -> 227 ms
@@ -179,7 +181,7 @@ struct fdas_plan_s {
 
     // workspace
     int64_t spitch = 0;
-    float2 *d_spec = nullptr, *d_w0 = nullptr, *d_w1 = nullptr;
+    float2 *d_spec = nullptr, *d_w0 = nullptr;
     float *d_scale = nullptr;
     double *d_norm = nullptr;
     uint8_t *d_med = nullptr;   // median-select scratch
@@ -562,7 +564,7 @@ fdas_status run_spectrum(fdas_plan p, const float *x, const int64_t *offs, int64
                          hipStream_t st) {
     float2 *spec = p->d_spec + (int64_t)v0 * p->spitch;
     hipEvent_t e = p->begin(st);
-    HIPTRY(p, launch_rfft(x, nsamp, nb, p->d_w0, p->d_w1, spec, p->spitch, st, offs));
+    HIPTRY(p, launch_rfft(x, nsamp, nb, p->d_w0, spec, p->spitch, st, offs));
     p->end(0, e, st);
     if (p->opts.norm == FDAS_NORM_MEDIAN) {
         e = p->begin(st);
@@ -1191,7 +1193,7 @@ void fdas_plan_destroy(fdas_plan p) {
     for (auto &b : p->banks) (void)hipFree(b.d);
     for (auto &t : p->tables) (void)hipFree(t.d);
     for (auto &t : p->ltabs) (void)hipFree(t.second.first);
-    void *dev[] = {p->d_spec, p->d_w0, p->d_w1, p->d_scale, p->d_norm, p->d_med, p->d_thr, p->d_state, p->d_offs,
+    void *dev[] = {p->d_spec, p->d_w0, p->d_scale, p->d_norm, p->d_med, p->d_thr, p->d_state, p->d_offs,
                    p->d_plane, p->d_maxv, p->d_zarg, p->d_counts, p->d_offsets, p->d_rec, p->d_pyr, p->d_rpts, p->d_rpow, p->d_dd[0], p->d_dd[1], p->d_delays, p->d_csum, p->d_cpad, p->d_lmed,
                    p->d_hitems, p->d_hstarts};
     for (void *q : dev)
@@ -1254,7 +1256,6 @@ fdas_status fdas_plan_create(fdas_plan *out, int64_t max_nsamp, int32_t max_seri
     p->spitch = round_up(half + 1, 2);
     if ((s = dalloc(p, &p->d_spec, (int64_t)max_series * p->spitch, "spectra")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_w0, (int64_t)max_series * half, "fft scratch")) != FDAS_OK) return bail(s);
-    if ((s = dalloc(p, &p->d_w1, (int64_t)max_series * half, "fft scratch")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_scale, max_series, "scales")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_norm, max_series, "norms")) != FDAS_OK) return bail(s);
     if ((s = dalloc(p, &p->d_med, (int64_t)median_scratch_bytes(max_series), "median scratch")) != FDAS_OK)

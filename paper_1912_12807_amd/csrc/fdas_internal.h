@@ -75,11 +75,11 @@ struct DevCand {
 // K1: real FFT of nseries series of n samples: n even, >= 8, with n/2 a product of
 // powers of 2, 3 and 5 (fft_length_supported).
 bool fft_length_supported(int64_t n);
-// x: [nseries][n] float32; w0, w1: scratch [nseries][n/2] complex; spec: [nseries][spitch]
-// complex receiving A_k for k = 0..n/2.
+// x: [nseries][n] float32; w0: scratch [nseries][n/2] complex (unused when
+// n/2 <= 8192); spec: [nseries][spitch] complex receiving A_k for k = 0..n/2.
 // offs (device, optional): series b starts at x + 2 offs[b] floats (ragged batches);
 // otherwise series b starts at x + b n.
-hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float2 *w1,
+hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0,
                        float2 *spec, int64_t spitch, hipStream_t st, const int64_t *offs = nullptr);
 
 // state[0] = state[1] = 0 (a kernel, so that captured graphs hold no memset node).

@@ -22,9 +22,12 @@
 //   * larger M = M1 M2 (four-step): pass 1 transforms columns n2 of
 //     z[n1 M2 + n2] over n1 (length M1, T consecutive columns per workgroup),
 //     multiplies by exp(-2 pi i n2 k1 / M) and writes Y[k1 M2 + n2]; pass 2
-//     transforms rows k1 of Y over n2 (length M2, T consecutive rows) and
-//     writes Z[k1 + M1 k2]; a last pass splits Z into A. Each pass reads and
-//     writes every point once, T consecutive complex values per access group.
+//     transforms rows k1 of Y over n2 (length M2) and splits them into A:
+//     a workgroup holds T/2 consecutive rows and their T/2 mirror rows
+//     M1 - k1, where the partners Z_{M-k} of its outputs lie. Each pass reads
+//     and writes every point once, T (pass 1) or T/2 (pass 2) consecutive
+//     complex values per access group. (With T = 1, possible only for odd
+//     factors, pass 2 writes Z[k1 + M1 k2] and a last pass splits Z into A.)
 // Twiddles come from sincospi of 2 j / n (exact for power-of-two n).
 #include "dft_small.h"
 #include "fdas_internal.h"
@@ -247,12 +250,12 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(const float2 *__restri
     }
 }
 
-// Four-step pass 2: T rows k1 = k10..k10+T-1 of Y, transform over n2 (length
-// M2), Z[k1 + M1 k2].
+// Four-step pass 2 without the split (T = 1): T rows k1 = k10..k10+T-1 of Y,
+// transform over n2 (length M2), Z[k1 + M1 k2] into the spectrum rows.
 template <int PC>
 __global__ __launch_bounds__(kFftThreads) void k_fft_rows(const float2 *__restrict__ Y, FftPlan fp, int M1,
                                                           int lgT, int64_t tiles_per_series, int64_t total_tiles,
-                                                          float2 *__restrict__ Z) {
+                                                          float2 *__restrict__ Z, int64_t zpitch) {
     const int T = 1 << lgT;
     extern __shared__ __align__(16) float2 fbuf[];
     const int64_t w = blockIdx.x;
@@ -270,19 +273,79 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(const float2 *__restri
     }
     __syncthreads();
     run_fft<PC>(fbuf, fp, T);
-    float2 *dst = Z + (int64_t)b * M + k10;
+    float2 *dst = Z + (int64_t)b * zpitch + k10;
     for (int e = threadIdx.x; e < T * M2; e += kFftThreads) {
         const int t = e & (T - 1), k2 = e >> lgT;
         dst[(int64_t)k2 * M1 + t] = fbuf[t * M2 + swz(k2, t, M2)];
     }
 }
 
-__global__ __launch_bounds__(256) void k_rfft_post(const float2 *__restrict__ Z, int64_t zpitch,
-                                                   float2 *__restrict__ A, int64_t apitch, int64_t M) {
+// Four-step pass 2 fused with the real split. Output k = k1 + M1 k2 needs
+// Z_{M-k}, which lies in row (M1 - k1) mod M1 at k2' = M2 - 1 - k2 (k1 > 0) or
+// (M2 - k2) mod M2 (k1 = 0). So the T lines of a workgroup hold T/2 "lower"
+// rows r = r0..r0+T/2-1 (r <= M1/2) in lines 0..T/2-1 and their mirrors
+// (M1 - r) mod M1 in lines T/2..T-1: after the row transforms every output of
+// these rows has both its points in LDS and A is written directly. A mirror
+// equal to its own row (r = 0, r = M1/2) is written from the lower line only;
+// the row-0 line also writes A_M (Z_M = Z_0).
+template <int PC>
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows_split(const float2 *__restrict__ Y, FftPlan fp, int M1,
+                                                                int lgT, int64_t tiles_per_series,
+                                                                int64_t total_tiles, float2 *__restrict__ A,
+                                                                int64_t apitch) {
+    const int T = 1 << lgT, H = T >> 1;
+    extern __shared__ __align__(16) float2 fbuf[];
+    const int64_t w = blockIdx.x;
+    const int64_t per_xcd = (total_tiles + 7) / 8;
+    const int64_t g = (w & 7) * per_xcd + (w >> 3);
+    if (g >= total_tiles) return;
+    const int b = (int)(g / tiles_per_series);
+    const int r0 = (int)(g - (int64_t)b * tiles_per_series) * H;
+    const int M2 = PC > 0 ? PC : fp.P;
+    const int64_t M = (int64_t)M1 * M2;
+    const int rmax = M1 / 2;   // last lower row
+    const float2 *src = Y + (int64_t)b * M;
+    // line t: its row, or -1 past the last lower row
+    auto row_of = [&](int t) -> int {
+        const int r = r0 + (t & (H - 1));
+        if (r > rmax) return -1;
+        return t < H ? r : (r == 0 ? 0 : M1 - r);
+    };
+    for (int e = threadIdx.x; e < T * M2; e += kFftThreads) {
+        const int t = e / M2, n2 = e - t * M2;
+        const int row = row_of(t);
+        if (row >= 0) fbuf[t * M2 + swz(n2, t, M2)] = src[(int64_t)row * M2 + n2];
+    }
+    __syncthreads();
+    run_fft<PC>(fbuf, fp, T);
+    float2 *dst = A + (int64_t)b * apitch;
+    for (int e = threadIdx.x; e < T * M2; e += kFftThreads) {
+        const int t = e & (T - 1), k2 = e >> lgT;
+        const int r = r0 + (t & (H - 1));
+        if (r > rmax || (t >= H && (r == 0 || 2 * r == M1))) continue;
+        const int row = t < H ? r : M1 - r;
+        const int pt = t ^ H;                                        // the mirror row's line
+        const int p2 = row == 0 ? (k2 == 0 ? 0 : M2 - k2) : M2 - 1 - k2;
+        const float2 zk = fbuf[t * M2 + swz(k2, t, M2)];
+        const float2 zm = fbuf[pt * M2 + swz(p2, pt, M2)];
+        const int64_t k = row + (int64_t)M1 * k2;
+        dst[k] = real_split(zk, zm, k, M);
+        if (row == 0 && k2 == 0) dst[M] = real_split(zk, zk, M, M);
+    }
+}
+
+// Real split in place after the T = 1 pass 2: one thread per pair (k, M - k)
+// reads Z_k and Z_{M-k} from the spectrum row and writes A_k and A_{M-k}
+// (k = 0: A_0 and A_M from Z_0), so every point is read once.
+__global__ __launch_bounds__(256) void k_rfft_split_pairs(float2 *__restrict__ A, int64_t apitch, int64_t M) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > M) return;
-    const float2 *z = Z + (int64_t)blockIdx.y * zpitch;
-    A[(int64_t)blockIdx.y * apitch + k] = real_split(z[k == M ? 0 : k], z[k == 0 ? 0 : M - k], k, M);
+    if (2 * k > M) return;
+    float2 *a = A + (int64_t)blockIdx.y * apitch;
+    const float2 zk = a[k];
+    const float2 zm = a[k == 0 ? 0 : M - k];
+    a[k] = real_split(zk, zm, k, M);
+    if (k == 0) a[M] = real_split(zk, zk, M, M);
+    else if (2 * k != M) a[M - k] = real_split(zm, zk, M - k, M);
 }
 
 namespace {
@@ -308,10 +371,27 @@ bool radix_plan(int P, FftPlan &fp) {
     return m == 1;
 }
 
-// Split M into M1 x M2 (both 5-smooth, at most kLdsPoints) as evenly as
-// possible, M2 a multiple of 4 where M allows, and the tile width T (columns or
-// rows per workgroup, dividing M2 and M1) so that T max(M1, M2) <= kLdsPoints.
-bool four_step_split(int64_t M, int &M1, int &M2, int &T) {
+struct FourStep {
+    int M1, M2;   // column and row lengths, M = M1 M2
+    int T1, T2;   // columns per workgroup of pass 1, lines per workgroup of pass 2
+};
+
+// Widest power-of-two tile (at most 64 lines) of lines of P points that fits
+// in LDS.
+int tile_lines(int64_t P) {
+    int t = 1;
+    while (t < 64 && P * (2 * t) <= kLdsPoints) t *= 2;
+    return t;
+}
+
+// Split M into M1 x M2 (both 5-smooth, at most kLdsPoints): the widest tile
+// T that divides both and fits in LDS for both (T1 = T consecutive columns in
+// pass 1), then the most even split. Pass 2 stages as many lines as fit (T2,
+// no divisibility needed: rows and mirrors are paired); T2 = 1 (M2 > 4096)
+// leaves the split to a pass of its own. (Choosing the split for the fewest
+// short runs per pass instead measured slower: 0.22 against 0.19 ms of FFT
+// on 128 series of 2^18 samples.)
+bool four_step_split(int64_t M, FourStep &fs) {
     int64_t best = -1;
     for (int64_t a = 1; a <= kLdsPoints; ++a) {
         if (M % a || !smooth5(a)) continue;
@@ -324,9 +404,7 @@ bool four_step_split(int64_t M, int &M1, int &M2, int &T) {
         const int64_t score = (int64_t)t * (1 << 20) - mx;
         if (score > best) {
             best = score;
-            M1 = (int)a;
-            M2 = (int)c;
-            T = t;
+            fs = FourStep{(int)a, (int)c, t, tile_lines(c)};
         }
     }
     return best >= 0;
@@ -338,8 +416,8 @@ bool fft_length_supported(int64_t n) {
     const int64_t M = n / 2;
     if (n < 8 || (n & 1) || !smooth5(M)) return false;
     if (M <= kLdsPoints) return true;
-    int M1 = 0, M2 = 0, T = 0;
-    return four_step_split(M, M1, M2, T);
+    FourStep fs;
+    return four_step_split(M, fs);
 }
 
 // Launch KERNEL<P> for a power-of-two length P known at compile time, or
@@ -360,7 +438,7 @@ bool fft_length_supported(int64_t n) {
     default: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;                     \
     }
 
-hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float2 *w1,
+hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0,
                        float2 *spec, int64_t spitch, hipStream_t st, const int64_t *offs) {
     const int64_t M = n / 2;
     if (n < 8 || (n & 1) || nseries < 1 || nseries > 65535 || !smooth5(M)) return hipErrorInvalidValue;
@@ -372,24 +450,37 @@ hipError_t launch_rfft(const float *x, int64_t n, int nseries, float2 *w0, float
                           offs, fp, spec, spitch);
         return hipGetLastError();
     }
-    int M1 = 0, M2 = 0, T = 0;
-    if (!four_step_split(M, M1, M2, T)) return hipErrorInvalidValue;
+    FourStep fs;
+    if (!four_step_split(M, fs)) return hipErrorInvalidValue;
+    const int M1 = fs.M1, M2 = fs.M2;
     FftPlan f1, f2;
     if (!radix_plan(M1, f1) || !radix_plan(M2, f2)) return hipErrorInvalidValue;
-    int lgT = 0;
-    while ((1 << lgT) < T) ++lgT;
+    auto lg = [](int t) {
+        int l = 0;
+        while ((1 << l) < t) ++l;
+        return l;
+    };
     {
+        const int T = fs.T1;
         const int64_t tps = M2 / T, total = tps * nseries;
         FDAS_FFT_DISPATCH(k_fft_cols, M1, dim3((unsigned)(8 * ((total + 7) / 8))), dim3(kFftThreads),
-                          (size_t)T * M1 * sizeof(float2), st, z, offs, f1, M2, lgT, tps, total, w0);
+                          (size_t)T * M1 * sizeof(float2), st, z, offs, f1, M2, lg(T), tps, total, w0);
+    }
+    const int T = fs.T2;
+    if (T >= 2) {
+        // rows and their mirrors together: the split needs no pass of its own
+        const int64_t tps = (M1 / 2 + T / 2) / (T / 2), total = tps * nseries;
+        FDAS_FFT_DISPATCH(k_fft_rows_split, M2, dim3((unsigned)(8 * ((total + 7) / 8))), dim3(kFftThreads),
+                          (size_t)T * M2 * sizeof(float2), st, w0, f2, M1, lg(T), tps, total, spec, spitch);
+        return hipGetLastError();
     }
     {
         const int64_t tps = M1 / T, total = tps * nseries;
         FDAS_FFT_DISPATCH(k_fft_rows, M2, dim3((unsigned)(8 * ((total + 7) / 8))), dim3(kFftThreads),
-                          (size_t)T * M2 * sizeof(float2), st, w0, f2, M1, lgT, tps, total, w1);
+                          (size_t)T * M2 * sizeof(float2), st, w0, f2, M1, lg(T), tps, total, spec, spitch);
     }
-    dim3 grid((unsigned)((M + 1 + 255) / 256), (unsigned)nseries);
-    hipLaunchKernelGGL(k_rfft_post, grid, dim3(256), 0, st, w1, M, spec, spitch, M);
+    dim3 grid((unsigned)((M / 2 + 1 + 255) / 256), (unsigned)nseries);
+    hipLaunchKernelGGL(k_rfft_split_pairs, grid, dim3(256), 0, st, spec, spitch, M);
     return hipGetLastError();
 }
 #undef FDAS_FFT_DISPATCH

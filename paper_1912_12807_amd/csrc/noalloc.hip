@@ -55,13 +55,13 @@ extern "C" fdas_status fdas_spectrum_noalloc(const float *series_dev, int64_t ns
     if (nseries < 1 || nseries > 65535 || nsamp < 8 || (nsamp & 1)) return FDAS_E_INVAL;
     if (!fft_length_supported(nsamp)) return FDAS_E_UNSUPPORTED;
     const int64_t half = nsamp / 2;
-    // scratch layout: FFT buffers w0, w1 [nseries][half], scales, norms, median scratch
+    // scratch layout: FFT buffer w0 [nseries][half], scales, norms, median scratch
     const size_t fft_bytes = align256((size_t)nseries * (size_t)half * sizeof(float2));
     const size_t scale_bytes = align256((size_t)nseries * sizeof(float));
     const size_t norm_bytes = align256((size_t)nseries * sizeof(double));
     const size_t med_bytes = align256(median_scratch_bytes(nseries));
     if ((size_t)half > kScratchBytes / sizeof(float2) ||
-        2 * fft_bytes + scale_bytes + norm_bytes + med_bytes > kScratchBytes)
+        fft_bytes + scale_bytes + norm_bytes + med_bytes > kScratchBytes)
         return FDAS_E_INVAL;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
@@ -75,13 +75,12 @@ extern "C" fdas_status fdas_spectrum_noalloc(const float *series_dev, int64_t ns
     }
     unsigned char *b = static_cast<unsigned char *>(base);
     float2 *w0 = reinterpret_cast<float2 *>(b);
-    float2 *w1 = reinterpret_cast<float2 *>(b + fft_bytes);
-    float *scale = reinterpret_cast<float *>(b + 2 * fft_bytes);
-    double *norm = reinterpret_cast<double *>(b + 2 * fft_bytes + scale_bytes);
-    void *med = b + 2 * fft_bytes + scale_bytes + norm_bytes;
+    float *scale = reinterpret_cast<float *>(b + fft_bytes);
+    double *norm = reinterpret_cast<double *>(b + fft_bytes + scale_bytes);
+    void *med = b + fft_bytes + scale_bytes + norm_bytes;
     hipStream_t st = static_cast<hipStream_t>(stream);
     float2 *spec = reinterpret_cast<float2 *>(spec_dev);
-    if (launch_rfft(series_dev, nsamp, nseries, w0, w1, spec, half + 1, st) != hipSuccess ||
+    if (launch_rfft(series_dev, nsamp, nseries, w0, spec, half + 1, st) != hipSuccess ||
         launch_median_scale(spec, half + 1, half, nseries, scale, norm, med, st) != hipSuccess) {
         (void)hipGetLastError();
         return FDAS_E_DEVICE;

@@ -31,6 +31,7 @@ SPECTRUM_LENGTHS = [
     8, 64, 1 << 12, 1 << 14, 1 << 15, 1 << 17, 1 << 23,       # one workgroup up to 2^14, four-step above
     12, 30, 4374, 12000,                                      # N/2 = 6, 15, 3^7, 2^4 3 5^3: in one workgroup
     31250, 153600, 6291456,                                   # N/2 = 5^6, 2^10 3 5^2, 3 2^20: four-step
+    33592320,                                                 # N/2 = 2^9 3^8 5: rows of 4320, split pass
 ]
 
 
