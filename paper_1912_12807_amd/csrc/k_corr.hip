@@ -225,16 +225,23 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
     const int64_t ppitch = PYR == 2 ? pitch / 2 : pitch;
     bmax_t *pout = PYR ? pyr + (int64_t)b * psstride + (PYR == 2 ? 1 : 2) * (ks - g.rlo) : nullptr;
     int blk = 0, blk_end = 0;
-    float m0[8], m1[8];
-    uint32_t pv[8];   // PYR 1: the previous block's codes of both columns of a bin
+    // PYR 2: the running maximum of both parities of each bin. PYR 1: per
+    // bin one register with the upper 16 bits of each parity's running
+    // maximum power (parity p in half p), and the previous block's codes of
+    // both columns of two bins per register (16 bits each): registers are
+    // what keeps this instance at 3 waves per SIMD
+    float m0[8];
+    uint32_t m01[8], pv[4];
     if constexpr (PYR != 0) {
         blk = blk_of_row[z0];
         blk_end = blk_lo[blk + 1];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            m0[q] = m1[q] = 0.0f;
-            pv[q] = 0u;
+            m0[q] = 0.0f;
+            m01[q] = 0u;
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pv[q] = 0u;
     }
     // Kernel spectra and plane rows go through buffer resources: a
     // workgroup-uniform base and scalar offset plus the lane's fixed 32-bit
@@ -293,8 +300,20 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
                         m0[q] = max_nonneg(m0[q], pw);
                     }
                 } else if constexpr (PYR == 1) {
-                    if (p == 0) m0[q] = max_nonneg(m0[q], pw);
-                    else m1[q] = max_nonneg(m1[q], pw);
+                    // half p of m01 = max(half p, upper 16 bits of pw): one
+                    // 16-bit maximum with sub-dword operand selection (the
+                    // truncated bits are restored as all ones at the block end,
+                    // so the bound stays at or above every power)
+                    if (p == 0)
+                        asm("v_max_u16_sdwa %0, %1, %0 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE "
+                            "src0_sel:WORD_1 src1_sel:WORD_0"
+                            : "+v"(m01[q])
+                            : "v"(pw));
+                    else
+                        asm("v_max_u16_sdwa %0, %1, %0 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE "
+                            "src0_sel:WORD_1 src1_sel:WORD_1"
+                            : "+v"(m01[q])
+                            : "v"(pw));
                 }
             }
         }
@@ -313,18 +332,25 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int i = t + q * T;
+                    // PYR 1: cur = c0 | c1 << 8, the codes of the bin's columns
+                    // (each parity's maximum with its truncated low 16 bits
+                    // set: at or above the true maximum)
+                    const uint32_t cur = PYR == 1 ? bound_code(__uint_as_float((m01[q] << 16) | 0xffffu)) |
+                                                        (bound_code(__uint_as_float(m01[q] | 0xffffu)) << 8)
+                                                  : 0u;
                     if (i < Lv && ks + i < g.half) {
                         if constexpr (PYR == 2) {
                             prow[i] = bound_half(m0[q]);
                         } else {
-                            // columns 2i and 2i + 1: words 2i and 2i + 1 of the row
-                            // cur = c0 | c1 << 8; the bin's two words are the
-                            // bytes [p0, c0, p1, c1] of pv and cur (one permute)
-                            const uint32_t cur = bound_code(m0[q]) | (bound_code(m1[q]) << 8);
+                            // columns 2i and 2i + 1: words 2i and 2i + 1 of the
+                            // row; the bin's two words are the bytes
+                            // [p0, c0, p1, c1] of the previous codes and cur (one
+                            // permute)
+                            const uint32_t prev = (q & 1) ? pv[q >> 1] >> 16 : pv[q >> 1];
                             uint8_t *w = reinterpret_cast<uint8_t *>(prow + 2 * i);
                             uint8_t *wp = reinterpret_cast<uint8_t *>(prow - ppitch + 2 * i);
                             if (!first) {
-                                *reinterpret_cast<uint32_t *>(wp) = __builtin_amdgcn_perm(cur, pv[q], 0x05010400u);
+                                *reinterpret_cast<uint32_t *>(wp) = __builtin_amdgcn_perm(cur, prev, 0x05010400u);
                             } else if (z0 > 0) {
                                 wp[1] = (uint8_t)cur;
                                 wp[3] = (uint8_t)(cur >> 8);
@@ -337,10 +363,18 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
                                     w[2] = (uint8_t)(cur >> 8);
                                 }
                             }
-                            pv[q] = cur;
                         }
                     }
-                    m0[q] = m1[q] = 0.0f;
+                    // cur's two code bytes into half q & 1 of pv[q / 2] by a
+                    // byte permute, which reads bytes 0 and 1 of cur only: on
+                    // gfx950 the compiler packs the two codes with one
+                    // instruction whose bits 16..31 are not zero in practice
+                    // (merged with masks and ORs, they spoiled the other bin's
+                    // codes and the harmonic sums took 370 instead of 43 ms)
+                    if constexpr (PYR == 1)
+                        pv[q >> 1] = __builtin_amdgcn_perm(pv[q >> 1], cur, (q & 1) ? 0x01000504u : 0x07060100u);
+                    m0[q] = 0.0f;
+                    m01[q] = 0u;
                 }
                 ++blk;
                 if (zi + 1 < z1) blk_end = blk_lo[blk + 1];
@@ -361,12 +395,12 @@ __global__ __launch_bounds__(L / 8) void k_corr_power(FDAS_K4_PARAMS) {
     corr_power<L, PYR>(FDAS_K4_ARGS);
 }
 
-// Per-column maxima keep two running maxima per point: at the 4 waves per SIMD
-// that LDS allows, the compiler then has so few registers left that it
-// serialises the kernel-spectrum loads; 3 waves with the loads in flight
-// together are faster.
+// Per-column maxima: the two parities' running maxima share a register as
+// 16-bit halves, and the previous block's codes of two bins share one, which
+// fits the instance in 4 waves per SIMD (as many as LDS allows). With them in
+// 24 registers of their own it needed 152 and ran at 3 waves.
 template <int L>
-__global__ __launch_bounds__(L / 8) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_corr_power_cols(
+__global__ __launch_bounds__(L / 8) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_corr_power_cols(
     FDAS_K4_PARAMS) {
     corr_power<L, 1>(FDAS_K4_ARGS);
 }
