@@ -398,9 +398,11 @@ __global__ __launch_bounds__(L / 8) void k_corr_power(FDAS_K4_PARAMS) {
 // Per-column maxima: the two parities' running maxima share a register as
 // 16-bit halves, and the previous block's codes of two bins share one, which
 // fits the instance in 4 waves per SIMD (as many as LDS allows). With them in
-// 24 registers of their own it needed 152 and ran at 3 waves.
+// 24 registers of their own it needed 152 and ran at 3 waves. At L 1024 (a
+// different pass layout) 4 waves would spill registers, so that instance
+// keeps 3.
 template <int L>
-__global__ __launch_bounds__(L / 8) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_corr_power_cols(
+__global__ __launch_bounds__(L / 8) __attribute__((amdgpu_waves_per_eu(L == 1024 ? 3 : 4, L == 1024 ? 3 : 4))) void k_corr_power_cols(
     FDAS_K4_PARAMS) {
     corr_power<L, 1>(FDAS_K4_ARGS);
 }
