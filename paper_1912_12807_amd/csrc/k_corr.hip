@@ -228,8 +228,8 @@ __device__ __forceinline__ void corr_power(const float2 *__restrict__ spec, int6
     // PYR 2: the running maximum of both parities of each bin. PYR 1: per
     // bin one register with the upper 16 bits of each parity's running
     // maximum power (parity p in half p), and the previous block's codes of
-    // both columns of two bins per register (16 bits each): registers are
-    // what keeps this instance at 3 waves per SIMD
+    // both columns of two bins per register (16 bits each): the registers
+    // this saves fit the instance in 4 waves per SIMD
     float m0[8];
     uint32_t m01[8], pv[4];
     if constexpr (PYR != 0) {
