@@ -838,26 +838,33 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
     const size_t row = (size_t)ns + 8;   // per-thread counters, a cache line apart
     std::vector<int64_t> next(sorted_on_device ? 0 : (size_t)nth * row, 0);
     std::vector<char> bad((size_t)nth, 0);
-    over_threads([&](int w, int64_t i0, int64_t i1) {
-        for (int64_t i = i0; i < i1; ++i) {
-            const DevCand &d = p->h_rec[i];
-            if (d.b < 0 || d.b >= (int)B.vmap.size() || d.s < 0 || d.s > 5) {
-                bad[w] = 1;
-                return;
-            }
-            const Geometry &g = B.groups[B.vgroup[d.b]].g;
-            if (d.zq < -g.Z || d.zq > g.Z) {
-                bad[w] = 2;
-                return;
-            }
-            if (!sorted_on_device) ++next[(size_t)w * row + B.vmap[d.b]];
+    // a record's check: 0 valid, 1 unknown series or stage, 2 drift out of range
+    auto check = [&](const DevCand &d) -> int {
+        if (d.b < 0 || d.b >= (int)B.vmap.size() || d.s < 0 || d.s > 5) return 1;
+        const Geometry &g = B.groups[B.vgroup[d.b]].g;
+        return d.zq < -g.Z || d.zq > g.Z ? 2 : 0;
+    };
+    auto report = [&]() -> fdas_status {
+        for (int w = 0; w < nth; ++w) {
+            if (bad[w] == 1) return p->fail(FDAS_E_DEVICE, "internal error: candidate of an unknown series or stage");
+            if (bad[w] == 2) return p->fail(FDAS_E_DEVICE, "internal error: candidate without a maximising drift");
         }
-    });
-    for (int w = 0; w < nth; ++w) {
-        if (bad[w] == 1) return p->fail(FDAS_E_DEVICE, "internal error: candidate of an unknown series or stage");
-        if (bad[w] == 2) return p->fail(FDAS_E_DEVICE, "internal error: candidate without a maximising drift");
-    }
+        return FDAS_OK;
+    };
+    // device order is the output order when sorted on the device: the checks
+    // then run in the writing pass (one pass over the records instead of two)
     if (!sorted_on_device) {
+        over_threads([&](int w, int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const DevCand &d = p->h_rec[i];
+                if (const int e = check(d)) {
+                    bad[w] = (char)e;   // written only on failure: the flags share a cache line
+                    return;
+                }
+                ++next[(size_t)w * row + B.vmap[d.b]];
+            }
+        });
+        TRY(report());
         int64_t acc = 0;
         for (int v = 0; v < ns; ++v)
             for (int w = 0; w < nth; ++w) {
@@ -871,6 +878,12 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
         int64_t *nx = sorted_on_device ? nullptr : next.data() + (size_t)w * row;
         for (int64_t i = i0; i < i1; ++i) {
             const DevCand &d = p->h_rec[i];
+            if (sorted_on_device) {
+                if (const int e = check(d)) {
+                    bad[w] = (char)e;
+                    return;
+                }
+            }
             const int64_t k = nx ? nx[B.vmap[d.b]]++ : i;
             if (k >= lim) continue;
             const Geometry &g = B.groups[B.vgroup[d.b]].g;
@@ -889,6 +902,7 @@ fdas_status finish(fdas_plan p, const Batch &B, double dz, bool sorted_on_device
             c.fdot_hz_s = c.z_fund / (T * T);
         }
     });
+    TRY(report());
     *n_total = total;
     return total > cap ? FDAS_E_TRUNC : FDAS_OK;
 }
