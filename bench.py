@@ -224,7 +224,7 @@ def stats_summary(stats_csv: str, title: str, command: str) -> str:
     """Markdown table of a rocprofv3 --kernel-trace --stats CSV."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
-    out = [f"# {title}", "", "Command (repository root on the GPU box as $REPO):", "", "```", command, "```", "",
+    out = [f"# {title}", "", "Command (repository root on the GPU host as $REPO):", "", "```", command, "```", "",
            "| kernel | calls | avg us | share % |", "|---|---|---|---|"]
     for r in rows:
         out.append(f"| `{_kernel_key(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
@@ -256,7 +256,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, workload: str, command: str):
     f_scale = gib_kib / (sum(cf) / len(cf))
     w_scale = gib_kib / (sum(cw) / len(cw))
     res = {}
-    lines = [f"# HBM traffic per launch: {workload}", "", "Commands (repository root on the GPU box as $REPO):", "",
+    lines = [f"# HBM traffic per launch: {workload}", "", "Commands (repository root on the GPU host as $REPO):", "",
              "```", command, "```", "",
              f"Calibration: a 1 GiB device copy reads FETCH_SIZE {sum(cf) / len(cf):.0f} KiB and WRITE_SIZE "
              f"{sum(cw) / len(cw):.0f} KiB, so FETCH is scaled by {f_scale:.3f} and WRITE by {w_scale:.3f}.", "",
@@ -312,7 +312,7 @@ def counters_summary(csvs, title: str, command: str, bench_log: str) -> str:
                 continue
             val[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
             dur[k][(path, r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
-    out = [f"# Hardware counters per launch: {title}", "", "Commands (repository root on the GPU box as $REPO):", "",
+    out = [f"# Hardware counters per launch: {title}", "", "Commands (repository root on the GPU host as $REPO):", "",
            "```", command, "```", "",
            "Averages per launch over the dispatches of every pass. GRBM_GUI_ACTIVE is summed over the 8 XCDs and "
            "SQ_BUSY_CYCLES over the 32 shader engines; 'GRBM clock' = GRBM_GUI_ACTIVE / 8 / launch time. VALU "
@@ -385,7 +385,7 @@ def launch_tails_summary(trace_csv: str, title: str, command: str, steps: int) -
             int(r["Grid_Size_Z"])
         dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6   # ms
         fam.setdefault(name, []).append((wg, dur, int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
-    out = [f"# Launch tails: {title}", "", "Command (repository root on the GPU box as $REPO):", "", "```", command,
+    out = [f"# Launch tails: {title}", "", "Command (repository root on the GPU host as $REPO):", "", "```", command,
            "```", "",
            "Per kernel family, the largest launch's time per workgroup is taken as the full-machine rate; a "
            "launch's tail is its duration minus its workgroups at that rate. Gaps: idle device time between "
@@ -484,7 +484,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures the search on one GPU only; series shard across "
+        print("bench.py: the search is measured on one GPU only; series shard across "
               "GPUs without communication (see the design notes), but no multi-GPU figure is "
               "produced here", file=sys.stderr)
         sys.exit(2)

@@ -23,7 +23,7 @@ def gpu_available() -> bool:
 
 @pytest.fixture(scope="session")
 def fdas_gpu():
-    """The HIP binding on cuda:0; fails loudly if the library is missing on a GPU machine."""
+    """The HIP binding on cuda:0; fails loudly if the library is missing where a GPU is visible."""
     if not gpu_available():
         pytest.skip("no GPU visible")
     import paper_1912_12807_amd as fdas
